@@ -1,0 +1,90 @@
+"""Pins for the oracle's 2-D and batched forms (no GPU).
+
+2-D (Section 1: apply the 1-D filter to rows, then to columns) is pinned to
+the rectangle definition written out (naive2d), to a hand-derived example, to
+scipy's maximum_filter / minimum_filter, and to the columns-then-rows order.
+Batched is pinned to the per-series definition.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0610046_amd import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+
+
+def test_2d_worked_example():
+    for ex in GOLD["two_d"]:
+        for dt in (np.float32, np.int32, np.uint16):
+            a = np.array(ex["a"], dt)
+            for fn in (oracle.filter2d, oracle.naive2d):
+                mx, mn = fn(a, ex["w_rows"], ex["w_cols"])
+                assert mx.tolist() == ex["max"] and mn.tolist() == ex["min"]
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32, np.uint16])
+def test_2d_rows_then_columns_equals_rectangle(dt):
+    rng = synth.rng_for("tests", 20)
+    for it in range(40):
+        r = int(rng.integers(1, 40))
+        c = int(rng.integers(1, 40))
+        wr = int(rng.integers(1, r + 2))
+        wc = int(rng.integers(1, c + 2))
+        a = synth.small_alphabet(r * c, 7 if it % 2 else 60000, dt, rng).reshape(r, c)
+        mx, mn = oracle.filter2d(a, wr, wc)
+        nmx, nmn = oracle.naive2d(a, wr, wc)
+        assert np.array_equal(mx, nmx) and np.array_equal(mn, nmn)
+        # columns first, then rows: transpose, filter, transpose back
+        tmx, tmn = oracle.filter2d(np.ascontiguousarray(a.T), wc, wr)
+        assert np.array_equal(mx, tmx.T) and np.array_equal(mn, tmn.T)
+
+
+def test_2d_matches_scipy():
+    ndi = pytest.importorskip("scipy.ndimage")
+    rng = synth.rng_for("tests", 21)
+    a = synth.gaussian_field(64, 96, sigma=3.0, rng=rng)
+    for w in (3, 15, 63):
+        mx, mn = oracle.filter2d(a, w)
+        o = -(w // 2)
+        smx = ndi.maximum_filter(a, size=w, origin=o, mode="nearest")[:65 - w, :97 - w]
+        smn = ndi.minimum_filter(a, size=w, origin=o, mode="nearest")[:65 - w, :97 - w]
+        assert np.array_equal(mx, smx) and np.array_equal(mn, smn)
+
+
+def test_out_offsets():
+    offs = np.array([0, 5, 5, 12, 20], np.int64)
+    wins = np.array([3, 2, 8, 1], np.int64)
+    # lengths 5, 0, 7, 8 -> outputs 3, 0, 0, 8
+    assert oracle.out_offsets(offs, wins).tolist() == [0, 3, 3, 3, 11]
+
+
+def test_batched_equals_per_series():
+    rng = synth.rng_for("tests", 22)
+    packed, offs, wins = synth.batched_series(S=50, lo=1, hi=3000, wlo=1, whi=400, rng=rng)
+    oo, mx, mn = oracle.batched(packed, offs, wins)
+    for k in range(50):
+        a = packed[offs[k]:offs[k + 1]]
+        w = int(wins[k])
+        if a.size >= w:
+            v = np.lib.stride_tricks.sliding_window_view(a, w)
+            assert np.array_equal(mx[oo[k]:oo[k + 1]], v.max(axis=1))
+            assert np.array_equal(mn[oo[k]:oo[k + 1]], v.min(axis=1))
+        else:
+            assert oo[k] == oo[k + 1]
+
+
+def test_synth_inputs_are_canonical():
+    rng = synth.rng_for("tests", 23)
+    for a in (synth.random_walk(10000, np.float32, rng), synth.piecewise_monotone(10000, np.float32, rng),
+              synth.uniform01(10000, rng=rng), synth.gaussian_field(32, 32, rng=rng),
+              synth.ramp_f32(1000)):
+        assert synth.check_canonical(a)
+    x = np.array([-0.0, 1e-45, 2.0], np.float32)
+    synth.canonical(x)
+    assert synth.check_canonical(x) and not np.signbit(x[0])
+    r = synth.ramp_f32(100000)
+    assert np.all(np.diff(r) > 0)
