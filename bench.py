@@ -1,0 +1,213 @@
+"""Benchmark of the MI355X running max-min filter (one GPU).
+
+A step is one pass of the hot path over the n = 2**28 float32 random-walk
+series: the running max and min at each of the windows 16, 256, 4096 and
+65536 (four launches; the tile strategy serves the first two, the chunk
+strategy the last two).  ``value`` is input elements processed per second over
+the K timed steps (Gelem/s), inputs already resident in HBM.
+
+Also reported on the same JSON line (not part of ``value``):
+* ``per_window``   -- each window's launch time, Gelem/s and % of 8 TB/s
+  (algorithmic bytes: n*s read + 2*(n-w+1)*s written),
+* ``plain``        -- n = 2**20 float32, w = 64 (latency-bound),
+* ``batched``      -- 10,000 float32 random walks, lengths log-uniform in
+  [1e3, 1e6], windows uniform in [2, 1024], one batched call (graph replay),
+* ``image``        -- 8192 x 8192 float32, w x w windows, rows then columns,
+* ``roofline``     -- the dominant kernel against HBM peak,
+* ``cpu_baseline`` -- the CPU oracle (single thread) on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WINDOWS = (16, 256, 4096, 65536)
+
+
+def alg_bytes(n, w, s):
+    return n * s + 2 * max(0, n - w + 1) * s
+
+
+def timed(fn, iters, stream):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-log2", type=int, default=28)
+    ap.add_argument("--extras", type=int, default=1, help="also run plain / batched / image workloads")
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_cs_0610046_amd import binding as mm
+    from paper_cs_0610046_amd import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n = 1 << args.n_log2
+    t0 = time.time()
+    a = synth.random_walk(n, np.float32, synth.rng_for("large", 0))
+    print("[bench] generated n=2^%d walk in %.1fs" % (args.n_log2, time.time() - t0), file=sys.stderr, flush=True)
+    x = torch.from_numpy(a).to(dev)
+    outs = {w: (torch.empty(n - w + 1, dtype=torch.float32, device=dev),
+                torch.empty(n - w + 1, dtype=torch.float32, device=dev)) for w in WINDOWS}
+
+    def step():
+        for w in WINDOWS:
+            mm.maxmin_filter(x, w, outs[w][0], outs[w][1])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mm.maxmin_check_stream()
+    # per-launch timing with events on the launch stream (inside the timed steps)
+    ev = {w: [] for w in WINDOWS}
+    marks = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        for w in WINDOWS:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mm.maxmin_filter(x, w, outs[w][0], outs[w][1])
+            e1.record(stream)
+            marks.append((w, e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    for w, e0, e1 in marks:
+        ev[w].append(e0.elapsed_time(e1))
+    mm.maxmin_check_stream()
+    ms_per_step = wall * 1e3 / args.steps
+    value = len(WINDOWS) * n / (wall / args.steps) / 1e9
+    per_window = {}
+    for w in WINDOWS:
+        ms = float(np.mean(ev[w]))
+        gb = alg_bytes(n, w, 4) / (ms * 1e-3) / 1e9
+        per_window[str(w)] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                              "alg_GBs": round(gb, 1), "pct_hbm": round(100 * gb / HBM_PEAK_GBS, 1),
+                              "strategy": "tile" if mm.maxmin_plan(torch.float32, n, w) == 1 else "chunk"}
+    dom = max(WINDOWS, key=lambda w: np.mean(ev[w]))
+    dom_ms = float(np.mean(ev[dom]))
+    achieved = alg_bytes(n, dom, 4) / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_%s<float> (w=%d)" % (per_window[str(dom)]["strategy"], dom),
+                "alg_bytes_per_launch": alg_bytes(n, dom, 4), "avg_launch_ms": round(dom_ms, 4)}
+    print("[bench] headline %.1f Gelem/s, %.3f ms/step" % (value, ms_per_step), file=sys.stderr, flush=True)
+    del outs
+
+    extras = {}
+    if args.extras:
+        extras = run_extras(torch, mm, synth, dev, stream)
+
+    # CPU oracle on a bounded sample of the same workload (rank 0, N=1 only)
+    import oracle
+    m = min(n, 1 << args.cpu_sample_log2)
+    t0 = time.perf_counter()
+    for w in WINDOWS:
+        oracle.wedge(a[:m], w)
+    ct = time.perf_counter() - t0
+    cpu = {"value": round(len(WINDOWS) * m / ct / 1e9, 5), "unit": "Gelem/s", "cores": 1, "kind": "oracle",
+           "sample": "first 2^%d elements of the same float32 walk, windows %s, one thread (g++ -O2 "
+                     "monotonic-wedge oracle), %.1f s" % (args.cpu_sample_log2, list(WINDOWS), ct)}
+
+    line = {"metric": "Gelem/s and % HBM peak, batched vs plain kernel; serving p50/p99 latency",
+            "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "single float32 random walk n=2^%d, windows %s" % (args.n_log2, list(WINDOWS)),
+                       "n": n, "windows": list(WINDOWS)},
+            "per_window": per_window, "roofline": roofline, "cpu_baseline": cpu}
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+
+
+def run_extras(torch, mm, synth, dev, stream):
+    out = {}
+    # plain: n = 2^20 float32 uniform, w = 64
+    a = synth.uniform01(1 << 20)
+    x = torch.from_numpy(a).to(dev)
+    mx = torch.empty(x.numel() - 63, device=dev)
+    mn = torch.empty_like(mx)
+    for _ in range(5):
+        mm.maxmin_filter(x, 64, mx, mn)
+    ts = timed(lambda: mm.maxmin_filter(x, 64, mx, mn), 50, stream)
+    ms = float(np.median(ts))
+    out["plain"] = {"workload": "n=2^20 float32 uniform, w=64", "ms": round(ms, 4),
+                    "gelem_s": round(x.numel() / (ms * 1e-3) / 1e9, 2),
+                    "pct_hbm": round(100 * alg_bytes(x.numel(), 64, 4) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+    print("[bench] plain %.4f ms" % ms, file=sys.stderr, flush=True)
+    del x, mx, mn
+
+    # batched: 10,000 random walks, lengths log-uniform [1e3, 1e6], windows [2, 1024]
+    t0 = time.time()
+    packed, offs, wins = synth.batched_series()
+    print("[bench] generated batched (%d elems) in %.1fs" % (packed.size, time.time() - t0), file=sys.stderr,
+          flush=True)
+    oo = mm.maxmin_out_offsets(offs, wins)
+    xb = torch.from_numpy(packed).to(dev)
+    del packed
+    d_off, d_w, d_oo = (torch.from_numpy(v).to(dev) for v in (offs, wins, oo))
+    total = int(oo[-1])
+    bmx = torch.empty(total, device=dev)
+    bmn = torch.empty(total, device=dev)
+    s2 = torch.cuda.Stream(dev)
+    with torch.cuda.stream(s2):
+        for _ in range(3):
+            mm.maxmin_filter_batched(xb, d_off, d_w, d_oo, bmx, bmn)
+        ts = timed(lambda: mm.maxmin_filter_batched(xb, d_off, d_w, d_oo, bmx, bmn), 10, s2)
+    mm.maxmin_check_stream(s2)
+    ms = float(np.median(ts))
+    N = int(offs[-1])
+    ab = N * 4 + 2 * total * 4
+    out["batched"] = {"workload": "10000 float32 walks, n log-uniform [1e3,1e6], w uniform [2,1024], graph replay",
+                      "elements": N, "ms": round(ms, 4), "gelem_s": round(N / (ms * 1e-3) / 1e9, 2),
+                      "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+    print("[bench] batched %.3f ms" % ms, file=sys.stderr, flush=True)
+    del xb, bmx, bmn
+
+    # image: 8192 x 8192 float32 Gaussian field, w x w
+    img = synth.gaussian_field(8192, 8192)
+    xi = torch.from_numpy(img).to(dev)
+    del img
+    res = {}
+    for w in (3, 15, 63):
+        o1 = torch.empty((8192 - w + 1, 8192 - w + 1), device=dev)
+        o2 = torch.empty_like(o1)
+        for _ in range(2):
+            mm.maxmin_filter_2d(xi, w, w, o1, o2)
+        ts = timed(lambda: mm.maxmin_filter_2d(xi, w, w, o1, o2), 5, stream)
+        ms = float(np.median(ts))
+        ab = 8192 * 8192 * 4 + 2 * o1.numel() * 4
+        res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(8192 * 8192 / (ms * 1e-3) / 1e9, 2),
+                       "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+        del o1, o2
+    out["image"] = {"workload": "8192x8192 float32 Gaussian field + noise, rows then columns", "per_window": res}
+    print("[bench] image done", file=sys.stderr, flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    main()

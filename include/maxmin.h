@@ -1,0 +1,164 @@
+/*
+ * maxmin.h -- C ABI of the MI355X (gfx950) running max-min filter library.
+ *
+ * The running max-min filter (D. Lemire, "Streaming Maximum-Minimum Filter
+ * Using No More than Three Comparisons per Element", Section 1): for a series
+ * a_0 .. a_{n-1} and a window width w, compute for every window [j, j+w)
+ *     max[j] = max{a_j, ..., a_{j+w-1}},   min[j] = min{a_j, ..., a_{j+w-1}},
+ * for j = 0 .. n-w (0-based, valid windows only: n_out = max(0, n-w+1)).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named d_* are DEVICE pointers (hipMalloc'd, or torch CUDA
+ *     tensors); pointers named h_* are HOST pointers.  The caller owns all of
+ *     them; the library never frees or retains them past the call (except
+ *     the state a maxmin_stream_t handle owns, see below).
+ *   - Device pointers must be aligned to the element size; any such
+ *     alignment is accepted.  d_max, d_min and the input must not overlap.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default
+ *     stream).  Every call enqueues its work on that stream and returns
+ *     without synchronising; results are ready once the stream has reached
+ *     the call.  Calls that overlap on different streams are independent
+ *     (the library keeps its scratch memory per stream).
+ *   - Values are only compared and selected, never combined arithmetically,
+ *     so results are bit-exact.  Float inputs must be NaN-free; a window
+ *     holding both +0.0 and -0.0 returns one of them unspecified.
+ *   - Sizes and offsets are int64.  w > n is not an error: it yields no
+ *     output.
+ *   - Return value: MAXMIN_OK (0) or a negative maxmin_status_t.  On error
+ *     nothing is enqueued and maxmin_last_error() describes the failure
+ *     (thread-local).  No entry point throws or aborts.
+ */
+#ifndef MAXMIN_H
+#define MAXMIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MAXMIN_F32 = 0,
+  MAXMIN_F64 = 1,
+  MAXMIN_I32 = 2, /* signed order */
+  MAXMIN_U16 = 3  /* unsigned order */
+} maxmin_dtype_t;
+
+typedef enum {
+  MAXMIN_OK = 0,
+  MAXMIN_EINVAL = -1,      /* bad argument (w < 1, n < 0, null pointer with work to do, bad ld, ...) */
+  MAXMIN_ENOMEM = -2,      /* the library could not allocate its scratch memory */
+  MAXMIN_EDEVICE = -3,     /* a HIP call failed */
+  MAXMIN_EBUSY = -4,       /* scratch memory would have to grow while the stream is being captured */
+  MAXMIN_EUNSUPPORTED = -5 /* dtype or size outside what this build supports */
+} maxmin_status_t;
+
+/* Strategies a call may use; all produce identical bits. */
+typedef enum {
+  MAXMIN_STRATEGY_AUTO = 0,  /* planner / autotuner decides */
+  MAXMIN_STRATEGY_TILE = 1,  /* LDS tile: power-of-two block prefix/suffix plus one middle block (w <= 1024) */
+  MAXMIN_STRATEGY_CHUNK = 2  /* window-aligned chunks with look-back over chunk aggregates (any w) */
+} maxmin_strategy_t;
+
+/*
+ * maxmin_filter -- one series (Section 1 definition).
+ *   d_in  : n elements of `dtype`, contiguous.
+ *   d_max, d_min : n_out = max(0, n-w+1) elements each, contiguous.
+ * Errors: EINVAL if w < 1, n < 0, or a pointer is null while n_out > 0.
+ */
+int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max,
+                  void* d_min, void* stream);
+
+/*
+ * maxmin_filter_batched -- S independent series in one packed buffer, each
+ * with its own window (Section 1 definition applied per series).
+ *   d_in_offsets [S+1] : series k is d_in[d_in_offsets[k] .. d_in_offsets[k+1]),
+ *                        non-decreasing, d_in_offsets[0] = 0.
+ *   d_windows    [S]   : w_k >= 1.
+ *   d_out_offsets[S+1] : series k writes its max(0, n_k-w_k+1) outputs to
+ *                        d_max/d_min[d_out_offsets[k] ..]; computed by
+ *                        maxmin_out_offsets (host) from the same arrays.
+ * All three arrays are DEVICE int64 arrays.  Their contents are not
+ * validated on the host (that would need a synchronisation); malformed
+ * offsets are undefined behaviour.
+ * Errors: EINVAL if S < 0 or a pointer is null while S > 0.
+ */
+int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offsets,
+                          const int64_t* d_windows, const int64_t* d_out_offsets,
+                          int64_t S, void* d_max, void* d_min, void* stream);
+
+/*
+ * maxmin_out_offsets -- host helper: h_out_offsets[0] = 0 and
+ * h_out_offsets[k+1] = h_out_offsets[k] + max(0, n_k - w_k + 1), with
+ * n_k = h_in_offsets[k+1] - h_in_offsets[k].  All arrays are HOST arrays.
+ * Errors: EINVAL on null pointers, decreasing offsets or a window < 1.
+ */
+int maxmin_out_offsets(const int64_t* h_in_offsets, const int64_t* h_windows, int64_t S,
+                       int64_t* h_out_offsets);
+
+/*
+ * Streams -- the filter applied to a series that arrives in chunks, with
+ * zero stream latency (Section 1's definition of stream latency): each push
+ * emits exactly the windows whose last sample is in the chunk, so the
+ * concatenation of all pushes' outputs equals maxmin_filter over the
+ * concatenated input.  The handle owns a device-resident carry of the last
+ * min(t, w-1) samples (t = samples pushed so far, int64) and a host copy
+ * of t; nothing else is kept.
+ *
+ * maxmin_stream_create: allocates the handle and its device carry on the
+ *   current device.  Errors: EINVAL (w < 1, bad dtype, null out), ENOMEM.
+ * maxmin_stream_push: d_chunk has m elements; d_max/d_min must hold at least
+ *   m elements each; *h_n_out receives max(0, t+m-w+1) - max(0, t-w+1),
+ *   computed on the host before anything is enqueued.  Pushes on one handle
+ *   must be issued in order on one stream (each reads the carry the
+ *   previous one wrote).  Errors: EINVAL (null handle, m < 0, null pointers
+ *   with work to do).
+ * maxmin_stream_destroy: frees the handle (after synchronising the device
+ *   memory it owns).  NULL is accepted.
+ * maxmin_stream_samples: samples pushed so far (t), or -1 for NULL.
+ */
+typedef struct maxmin_stream maxmin_stream_t;
+int maxmin_stream_create(int dtype, int64_t w, maxmin_stream_t** out);
+int maxmin_stream_push(maxmin_stream_t* st, const void* d_chunk, int64_t m, void* d_max,
+                       void* d_min, int64_t* h_n_out, void* stream);
+int maxmin_stream_destroy(maxmin_stream_t* st);
+int64_t maxmin_stream_samples(const maxmin_stream_t* st);
+
+/*
+ * maxmin_filter_2d -- the 1-D filter applied to rows, then to columns
+ * (Section 1, images): for a row-major image with leading dimension ld_in
+ * (elements), outputs (rows-w_rows+1) x (cols-w_cols+1) with leading
+ * dimension ld_out:
+ *   max[r][c] = max over a[r..r+w_rows)[c..c+w_cols),  min likewise.
+ * Errors: EINVAL if a window < 1, rows/cols < 0, ld_in < cols,
+ * ld_out < output width, or a null pointer with work to do.
+ */
+int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int64_t ld_in,
+                     int64_t w_rows, int64_t w_cols, void* d_max, void* d_min, int64_t ld_out,
+                     void* stream);
+
+/* Force a strategy for subsequent 1-D calls from this process (AUTO restores
+ * the planner).  Used by tests to check that every strategy gives the same
+ * bits.  Errors: EINVAL on an unknown value. */
+int maxmin_set_strategy(int strategy);
+
+/* Strategy the planner would use for (dtype, n, w): a maxmin_strategy_t. */
+int maxmin_plan(int dtype, int64_t n, int64_t w);
+
+/* Synchronise `stream` (void* hipStream_t) and check the library's device
+ * status words for it: MAXMIN_EDEVICE if a chunk-strategy look-back wait on
+ * that stream ever gave up (its results are then invalid; not expected in
+ * normal operation), else MAXMIN_OK. */
+int maxmin_check_stream(void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char* maxmin_last_error(void);
+
+/* Library version string. */
+const char* maxmin_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAXMIN_H */

@@ -1,0 +1,233 @@
+"""Thin Python binding of libmaxmin's C ABI (``include/maxmin.h``).
+
+Argument marshalling only: every step of the filter runs in the library's
+gfx950 kernels.  Functions carry the C names; array arguments are torch CUDA
+tensors (device memory and streams are torch's), offsets for the host helper
+are numpy arrays.  If the library has not been built, every entry point
+raises -- there is no fallback.
+"""
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libmaxmin.so")
+
+MAXMIN_OK, MAXMIN_EINVAL, MAXMIN_ENOMEM, MAXMIN_EDEVICE, MAXMIN_EBUSY, MAXMIN_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STRATEGY_AUTO, STRATEGY_TILE, STRATEGY_CHUNK = 0, 1, 2
+
+_lock = threading.Lock()
+_lib = None
+
+
+class MaxMinError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("maxmin error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libmaxmin.so (built by ``paper_cs_0610046_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmaxmin.so is not built (%s); run __graft_entry__.build() or "
+                               "python paper_cs_0610046_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.maxmin_filter.argtypes = [ci, vp, i64, i64, vp, vp, vp]
+        L.maxmin_filter_batched.argtypes = [ci, vp, vp, vp, vp, i64, vp, vp, vp]
+        L.maxmin_out_offsets.argtypes = [vp, vp, i64, vp]
+        L.maxmin_stream_create.argtypes = [ci, i64, ctypes.POINTER(vp)]
+        L.maxmin_stream_push.argtypes = [vp, vp, i64, vp, vp, i64p, vp]
+        L.maxmin_stream_destroy.argtypes = [vp]
+        L.maxmin_stream_samples.argtypes = [vp]
+        L.maxmin_stream_samples.restype = i64
+        L.maxmin_filter_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, vp, vp, i64, vp]
+        L.maxmin_set_strategy.argtypes = [ci]
+        L.maxmin_plan.argtypes = [ci, i64, i64]
+        L.maxmin_check_stream.argtypes = [vp]
+        L.maxmin_last_error.restype = ctypes.c_char_p
+        L.maxmin_version.restype = ctypes.c_char_p
+        for f in ("maxmin_filter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
+                  "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_set_strategy",
+                  "maxmin_plan", "maxmin_check_stream"):
+            getattr(L, f).restype = ci
+        _lib = L
+        return L
+
+
+def _check(code):
+    if code != MAXMIN_OK:
+        raise MaxMinError(code, lib().maxmin_last_error().decode())
+
+
+_TORCH_CODES = None
+
+
+def dtype_code(dtype):
+    """maxmin_dtype_t of a torch or numpy dtype."""
+    global _TORCH_CODES
+    if _TORCH_CODES is None:
+        import torch
+        _TORCH_CODES = {torch.float32: 0, torch.float64: 1, torch.int32: 2, torch.uint16: 3}
+    if dtype in _TORCH_CODES:
+        return _TORCH_CODES[dtype]
+    d = np.dtype(dtype)
+    return {np.dtype(np.float32): 0, np.dtype(np.float64): 1, np.dtype(np.int32): 2, np.dtype(np.uint16): 3}[d]
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _cuda_1d(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def n_out(n, w):
+    return max(0, int(n) - int(w) + 1)
+
+
+def maxmin_filter(x, w, out_max=None, out_min=None, stream=None):
+    """Running max and min of every window [j, j+w) of the 1-D tensor x."""
+    import torch
+    _cuda_1d(x, "x")
+    k = n_out(x.numel(), w)
+    if out_max is None:
+        out_max = torch.empty(k, dtype=x.dtype, device=x.device)
+    if out_min is None:
+        out_min = torch.empty(k, dtype=x.dtype, device=x.device)
+    _check(lib().maxmin_filter(dtype_code(x.dtype), _ptr(x), x.numel(), int(w), _ptr(out_max), _ptr(out_min),
+                               _stream(stream)))
+    return out_max, out_min
+
+
+def maxmin_out_offsets(in_offsets, windows):
+    """Host helper: output offsets of a packed batch (numpy int64 arrays)."""
+    in_offsets = np.ascontiguousarray(in_offsets, np.int64)
+    windows = np.ascontiguousarray(windows, np.int64)
+    S = windows.size
+    out = np.zeros(S + 1, np.int64)
+    _check(lib().maxmin_out_offsets(in_offsets.ctypes.data, windows.ctypes.data if S else None, S,
+                                    out.ctypes.data))
+    return out
+
+
+def maxmin_filter_batched(packed, in_offsets, windows, out_offsets, out_max=None, out_min=None, stream=None):
+    """S series packed in one tensor, each with its own window.
+
+    ``in_offsets`` (S+1), ``windows`` (S) and ``out_offsets`` (S+1) are int64
+    CUDA tensors; ``out_offsets`` comes from :func:`maxmin_out_offsets`.
+    ``total_out`` outputs are allocated if not given (needs out_offsets[-1]
+    on the host: pass the outputs to avoid that read).
+    """
+    import torch
+    _cuda_1d(packed, "packed")
+    S = windows.numel()
+    if out_max is None or out_min is None:
+        total = int(out_offsets[-1].item()) if S else 0
+        out_max = torch.empty(total, dtype=packed.dtype, device=packed.device) if out_max is None else out_max
+        out_min = torch.empty(total, dtype=packed.dtype, device=packed.device) if out_min is None else out_min
+    _check(lib().maxmin_filter_batched(dtype_code(packed.dtype), _ptr(packed), _ptr(in_offsets), _ptr(windows),
+                                       _ptr(out_offsets), S, _ptr(out_max), _ptr(out_min), _stream(stream)))
+    return out_max, out_min
+
+
+class MaxMinStream:
+    """maxmin_stream_create / push / destroy: zero-latency chunked filtering."""
+
+    def __init__(self, dtype, w):
+        self.dtype = dtype
+        self.w = int(w)
+        h = ctypes.c_void_p()
+        _check(lib().maxmin_stream_create(dtype_code(dtype), self.w, ctypes.byref(h)))
+        self._h = h
+
+    def push(self, chunk, out_max=None, out_min=None, stream=None):
+        import torch
+        _cuda_1d(chunk, "chunk")
+        m = chunk.numel()
+        if out_max is None:
+            out_max = torch.empty(m, dtype=chunk.dtype, device=chunk.device)
+        if out_min is None:
+            out_min = torch.empty(m, dtype=chunk.dtype, device=chunk.device)
+        k = ctypes.c_int64(0)
+        _check(lib().maxmin_stream_push(self._h, _ptr(chunk), m, _ptr(out_max), _ptr(out_min), ctypes.byref(k),
+                                        _stream(stream)))
+        return out_max[:k.value], out_min[:k.value]
+
+    @property
+    def samples(self):
+        return lib().maxmin_stream_samples(self._h)
+
+    def close(self):
+        if self._h:
+            lib().maxmin_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def maxmin_stream_create(dtype, w):
+    return MaxMinStream(dtype, w)
+
+
+def maxmin_filter_2d(img, w_rows, w_cols=None, out_max=None, out_min=None, stream=None):
+    """Rows, then columns: max/min over every w_rows x w_cols rectangle."""
+    import torch
+    if not img.is_cuda or img.dim() != 2 or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D CUDA tensor with unit column stride")
+    w_cols = w_rows if w_cols is None else w_cols
+    rows, cols = img.shape
+    orr, occ = n_out(rows, w_rows), n_out(cols, w_cols)
+    if out_max is None:
+        out_max = torch.empty((orr, occ), dtype=img.dtype, device=img.device)
+    if out_min is None:
+        out_min = torch.empty((orr, occ), dtype=img.dtype, device=img.device)
+    ld_out = out_max.stride(0) if orr and occ else max(occ, 1)
+    _check(lib().maxmin_filter_2d(dtype_code(img.dtype), _ptr(img), rows, cols, img.stride(0) if rows else cols,
+                                  int(w_rows), int(w_cols), _ptr(out_max), _ptr(out_min), ld_out, _stream(stream)))
+    return out_max, out_min
+
+
+def maxmin_set_strategy(strategy):
+    _check(lib().maxmin_set_strategy(int(strategy)))
+
+
+def maxmin_plan(dtype, n, w):
+    return lib().maxmin_plan(dtype_code(dtype), int(n), int(w))
+
+
+def maxmin_check_stream(stream=None):
+    _check(lib().maxmin_check_stream(_stream(stream)))
+
+
+def maxmin_last_error():
+    return lib().maxmin_last_error().decode()
+
+
+def maxmin_version():
+    return lib().maxmin_version().decode()

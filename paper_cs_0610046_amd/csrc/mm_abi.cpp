@@ -1,0 +1,525 @@
+// C ABI of libmaxmin: argument checks, the planner, per-stream scratch
+// memory, the batched graph cache and stream-state handles.  All compute is
+// in the gfx950 kernels (mm_kernels_*.hip); nothing here touches values.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <utility>
+
+#include "maxmin.h"
+#include "mm_launch.hpp"
+
+namespace {
+
+using mm::JobArgs;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return MAXMIN_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(MAXMIN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t dsize(int dt) {
+  switch (dt) {
+    case MAXMIN_F32: return 4;
+    case MAXMIN_F64: return 8;
+    case MAXMIN_I32: return 4;
+    case MAXMIN_U16: return 2;
+    default: return 0;
+  }
+}
+
+bool aligned(const void* p, size_t s) { return ((uintptr_t)p % s) == 0; }
+
+std::atomic<int> g_force{0};
+
+int env_strategy() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("MAXMIN_FORCE_STRATEGY");
+    v = 0;
+    if (e && (!strcmp(e, "tile") || !strcmp(e, "1"))) v = MAXMIN_STRATEGY_TILE;
+    if (e && (!strcmp(e, "chunk") || !strcmp(e, "2"))) v = MAXMIN_STRATEGY_CHUNK;
+  }
+  return v;
+}
+
+// Planner: the tile strategy covers w <= 1024; the chunk strategy any w.
+int plan_strategy(int dt, int64_t n, int64_t w) {
+  (void)dt;
+  (void)n;
+  int f = g_force.load();
+  if (!f) f = env_strategy();
+  if (f == MAXMIN_STRATEGY_CHUNK) return MAXMIN_STRATEGY_CHUNK;
+  if (f == MAXMIN_STRATEGY_TILE && w <= mm::kTileMaxW) return MAXMIN_STRATEGY_TILE;
+  return w <= mm::kTileMaxW ? MAXMIN_STRATEGY_TILE : MAXMIN_STRATEGY_CHUNK;
+}
+
+// ------------------------------------------------------------ workspaces
+typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*> GraphKey;
+
+struct Workspace {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mm::Ctl* ctl = nullptr;
+  uint64_t* ring = nullptr;
+  uint32_t ring_lg = 0;
+  void* descs = nullptr;
+  int64_t desc_cap = 0;
+  int64_t* pre = nullptr;  // 2 * pre_cap int64
+  int64_t pre_cap = 0;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+bool capturing(hipStream_t s) {
+  if (!s) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
+void drop_graphs(Workspace* ws) {
+  for (auto& kv : ws->graphs) hipGraphExecDestroy(kv.second);
+  ws->graphs.clear();
+}
+
+// Any growth of scratch memory happens outside graph capture: it allocates
+// and initialises synchronously.
+int grow_guard(Workspace* ws, const char* what) {
+  if (capturing(ws->stream))
+    return fail(MAXMIN_EBUSY, "%s: scratch memory must grow while the stream is being captured; "
+                              "run the same call once before capturing", what);
+  hipError_t e = ws->stream ? hipStreamSynchronize(ws->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, what);
+  drop_graphs(ws);
+  return MAXMIN_OK;
+}
+
+int get_ws(hipStream_t s, Workspace** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> g(g_mu);
+  auto key = std::make_pair(dev, s);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) {
+    *out = it->second;
+    return MAXMIN_OK;
+  }
+  Workspace* ws = new Workspace;
+  ws->device = dev;
+  ws->stream = s;
+  if (capturing(s)) {
+    delete ws;
+    return fail(MAXMIN_EBUSY, "first use of a stream must not be inside graph capture");
+  }
+  e = hipMalloc((void**)&ws->ctl, sizeof(mm::Ctl));
+  if (e != hipSuccess) {
+    delete ws;
+    return fail(MAXMIN_ENOMEM, "hipMalloc(control words): %s", hipGetErrorString(e));
+  }
+  mm::Ctl init = {0u, 0u, 1u, 0u};
+  e = hipMemcpy(ws->ctl, &init, sizeof init, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(ws->ctl);
+    delete ws;
+    return hip_fail(e, "hipMemcpy(control words)");
+  }
+  g_ws[key] = ws;
+  *out = ws;
+  return MAXMIN_OK;
+}
+
+constexpr uint32_t kRingMaxLg = 20;  // 2^20 records (32 MiB); larger launches lap the ring
+
+int ensure_ring(Workspace* ws, int64_t ntiles) {
+  uint32_t lg = 10;
+  while (lg < kRingMaxLg && (int64_t(1) << lg) < ntiles) ++lg;
+  if (ws->ring && ws->ring_lg >= lg) return MAXMIN_OK;
+  int r = grow_guard(ws, "look-back records");
+  if (r) return r;
+  if (ws->ring) hipFree(ws->ring);
+  ws->ring = nullptr;
+  const size_t bytes = (size_t)4 * sizeof(uint64_t) << lg;
+  hipError_t e = hipMalloc((void**)&ws->ring, bytes);
+  if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(look-back records, %zu B): %s", bytes, hipGetErrorString(e));
+  e = hipMemset(ws->ring, 0, bytes);  // tag 0 never validates
+  if (e != hipSuccess) return hip_fail(e, "hipMemset(look-back records)");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  ws->ring_lg = lg;
+  return MAXMIN_OK;
+}
+
+int ensure_batch(Workspace* ws, int64_t S) {
+  if (ws->descs && ws->desc_cap >= S && ws->pre_cap >= S + 1) return MAXMIN_OK;
+  int r = grow_guard(ws, "batched descriptors");
+  if (r) return r;
+  if (ws->descs) hipFree(ws->descs);
+  if (ws->pre) hipFree(ws->pre);
+  ws->descs = nullptr;
+  ws->pre = nullptr;
+  const int64_t cap = std::max<int64_t>(S, 1024);
+  hipError_t e = hipMalloc(&ws->descs, (size_t)cap * mm::series_bytes());
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->pre, (size_t)2 * (cap + 1) * sizeof(int64_t));
+  if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(batched descriptors): %s", hipGetErrorString(e));
+  ws->desc_cap = cap;
+  ws->pre_cap = cap + 1;
+  return MAXMIN_OK;
+}
+
+int ensure_tmp(Workspace* ws, size_t bytes) {
+  if (ws->tmp && ws->tmp_bytes >= bytes) return MAXMIN_OK;
+  int r = grow_guard(ws, "2-D intermediate images");
+  if (r) return r;
+  if (ws->tmp) hipFree(ws->tmp);
+  ws->tmp = nullptr;
+  hipError_t e = hipMalloc(&ws->tmp, bytes);
+  if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(2-D intermediate, %zu B): %s", bytes, hipGetErrorString(e));
+  ws->tmp_bytes = bytes;
+  return MAXMIN_OK;
+}
+
+// Run one 1-D series (plain call or stream push) with the planned strategy.
+int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
+  const int strat = plan_strategy(dt, a.n, a.w);
+  hipError_t e;
+  if (strat == MAXMIN_STRATEGY_TILE) {
+    a.ntiles = mm::tile_count(a.n, a.w);
+    const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratTile));
+    e = mm::launch_1d(dt, mm::kStratTile, a, grid, st);
+  } else {
+    Workspace* ws = nullptr;
+    int r = get_ws(st, &ws);
+    if (r) return r;
+    a.ntiles = mm::chunk_count(a.n, a.w);
+    r = ensure_ring(ws, a.ntiles);
+    if (r) return r;
+    a.ring = ws->ring;
+    a.ring_lg = ws->ring_lg;
+    a.ctl = ws->ctl;
+    const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratChunk));
+    e = mm::launch_1d(dt, mm::kStratChunk, a, grid, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, what);
+  return ok();
+}
+
+bool g_graphs_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("MAXMIN_BATCHED_GRAPHS");
+    v = (e && !strcmp(e, "0")) ? 0 : 1;
+  }
+  return v == 1;
+}
+
+}  // namespace
+
+struct maxmin_stream {
+  int dt;
+  int64_t w;
+  int64_t t;
+  int device;
+  void* carry[2];
+  int cur;
+};
+
+extern "C" {
+
+const char* maxmin_last_error(void) { return g_err.c_str(); }
+
+const char* maxmin_version(void) { return "maxmin-gfx950 0.1"; }
+
+int maxmin_set_strategy(int strategy) {
+  if (strategy < MAXMIN_STRATEGY_AUTO || strategy > MAXMIN_STRATEGY_CHUNK)
+    return fail(MAXMIN_EINVAL, "maxmin_set_strategy: unknown strategy %d", strategy);
+  g_force.store(strategy);
+  return ok();
+}
+
+int maxmin_plan(int dtype, int64_t n, int64_t w) { return plan_strategy(dtype, n, w); }
+
+int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max, void* d_min, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_filter: unknown dtype %d", dtype);
+  if (w < 1) return fail(MAXMIN_EINVAL, "maxmin_filter: window w=%lld < 1", (long long)w);
+  if (n < 0) return fail(MAXMIN_EINVAL, "maxmin_filter: n=%lld < 0", (long long)n);
+  if (n < w) return ok();  // no complete window
+  if (!d_in || !d_max || !d_min) return fail(MAXMIN_EINVAL, "maxmin_filter: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
+    return fail(MAXMIN_EINVAL, "maxmin_filter: pointer not aligned to the element size");
+  JobArgs a;
+  a.mode = 0;
+  a.a = d_in;
+  a.na = n;
+  a.n = n;
+  a.w = w;
+  a.omax = d_max;
+  a.omin = d_min;
+  return run_series(dtype, a, (hipStream_t)stream, "maxmin_filter");
+}
+
+int maxmin_out_offsets(const int64_t* h_in_offsets, const int64_t* h_windows, int64_t S, int64_t* h_out_offsets) {
+  if (S < 0) return fail(MAXMIN_EINVAL, "maxmin_out_offsets: S < 0");
+  if (!h_in_offsets || !h_out_offsets || (S > 0 && !h_windows))
+    return fail(MAXMIN_EINVAL, "maxmin_out_offsets: null pointer");
+  h_out_offsets[0] = 0;
+  for (int64_t k = 0; k < S; ++k) {
+    const int64_t n = h_in_offsets[k + 1] - h_in_offsets[k];
+    if (n < 0) return fail(MAXMIN_EINVAL, "maxmin_out_offsets: offsets decrease at series %lld", (long long)k);
+    if (h_windows[k] < 1) return fail(MAXMIN_EINVAL, "maxmin_out_offsets: window < 1 at series %lld", (long long)k);
+    h_out_offsets[k + 1] = h_out_offsets[k] + std::max<int64_t>(0, n - h_windows[k] + 1);
+  }
+  return ok();
+}
+
+int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offsets, const int64_t* d_windows,
+                          const int64_t* d_out_offsets, int64_t S, void* d_max, void* d_min, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_filter_batched: unknown dtype %d", dtype);
+  if (S < 0) return fail(MAXMIN_EINVAL, "maxmin_filter_batched: S < 0");
+  if (S == 0) return ok();
+  if (!d_in || !d_in_offsets || !d_windows || !d_out_offsets || !d_max || !d_min)
+    return fail(MAXMIN_EINVAL, "maxmin_filter_batched: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
+    return fail(MAXMIN_EINVAL, "maxmin_filter_batched: pointer not aligned to the element size");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* ws = nullptr;
+  int r = get_ws(st, &ws);
+  if (r) return r;
+  if ((r = ensure_batch(ws, S))) return r;
+  if ((r = ensure_ring(ws, int64_t(1) << kRingMaxLg))) return r;
+
+  auto enqueue = [&]() -> hipError_t {
+    int64_t* pre_tile = ws->pre;
+    int64_t* pre_chunk = ws->pre + (S + 1);
+    hipError_t e = mm::launch_batched_setup(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min,
+                                            ws->descs, pre_tile, pre_chunk, st);
+    if (e != hipSuccess) return e;
+    JobArgs a;
+    a.mode = 1;
+    a.descs = ws->descs;
+    a.S = S;
+    a.pre = pre_tile;
+    e = mm::launch_1d(dtype, mm::kStratTile, a, mm::grid_cap(dtype, mm::kStratTile), st);
+    if (e != hipSuccess) return e;
+    a.pre = pre_chunk;
+    a.ring = ws->ring;
+    a.ring_lg = ws->ring_lg;
+    a.ctl = ws->ctl;
+    return mm::launch_1d(dtype, mm::kStratChunk, a, mm::grid_cap(dtype, mm::kStratChunk), st);
+  };
+
+  if (!st || !g_graphs_enabled() || capturing(st)) {
+    hipError_t e = enqueue();
+    if (e != hipSuccess) return hip_fail(e, "maxmin_filter_batched");
+    return ok();
+  }
+  // replay a captured graph of the three launches when the same call repeats
+  GraphKey key(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min);
+  auto it = ws->graphs.find(key);
+  if (it == ws->graphs.end()) {
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t e1 = enqueue();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (e1 != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return hip_fail(e1, "maxmin_filter_batched (capture)");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (ws->graphs.size() >= 64) drop_graphs(ws);
+    it = ws->graphs.emplace(key, ex).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second, st);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+int maxmin_stream_create(int dtype, int64_t w, maxmin_stream_t** out) {
+  const size_t s = dsize(dtype);
+  if (!out) return fail(MAXMIN_EINVAL, "maxmin_stream_create: null out");
+  *out = nullptr;
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_stream_create: unknown dtype %d", dtype);
+  if (w < 1) return fail(MAXMIN_EINVAL, "maxmin_stream_create: window w=%lld < 1", (long long)w);
+  maxmin_stream* st = new maxmin_stream;
+  st->dt = dtype;
+  st->w = w;
+  st->t = 0;
+  st->cur = 0;
+  hipGetDevice(&st->device);
+  const size_t bytes = (size_t)std::max<int64_t>(1, w - 1) * s;
+  st->carry[0] = st->carry[1] = nullptr;
+  hipError_t e = hipMalloc(&st->carry[0], bytes);
+  if (e == hipSuccess) e = hipMalloc(&st->carry[1], bytes);
+  if (e != hipSuccess) {
+    if (st->carry[0]) hipFree(st->carry[0]);
+    delete st;
+    return fail(MAXMIN_ENOMEM, "maxmin_stream_create: hipMalloc(carry, %zu B): %s", bytes, hipGetErrorString(e));
+  }
+  *out = st;
+  return ok();
+}
+
+int maxmin_stream_push(maxmin_stream_t* st, const void* d_chunk, int64_t m, void* d_max, void* d_min,
+                       int64_t* h_n_out, void* stream) {
+  if (!st) return fail(MAXMIN_EINVAL, "maxmin_stream_push: null handle");
+  if (m < 0) return fail(MAXMIN_EINVAL, "maxmin_stream_push: m < 0");
+  const int64_t c = std::min(st->t, st->w - 1);  // carried samples
+  const int64_t total = c + m;
+  const int64_t nout = std::max<int64_t>(0, total - st->w + 1);
+  if (h_n_out) *h_n_out = 0;
+  if (m == 0) return ok();
+  const size_t s = dsize(st->dt);
+  if (!d_chunk || (nout > 0 && (!d_max || !d_min))) return fail(MAXMIN_EINVAL, "maxmin_stream_push: null pointer");
+  if (!aligned(d_chunk, s) || (nout > 0 && (!aligned(d_max, s) || !aligned(d_min, s))))
+    return fail(MAXMIN_EINVAL, "maxmin_stream_push: pointer not aligned to the element size");
+  JobArgs a;
+  a.mode = 0;
+  a.a = st->carry[st->cur];
+  a.na = c;
+  a.b = d_chunk;
+  a.n = total;
+  a.w = st->w;
+  a.omax = d_max;
+  a.omin = d_min;
+  a.carry = st->w > 1 ? st->carry[1 - st->cur] : nullptr;
+  hipStream_t hs = (hipStream_t)stream;
+  if (nout > 0) {
+    int r = run_series(st->dt, a, hs, "maxmin_stream_push");
+    if (r) return r;
+  } else if (a.carry) {
+    hipError_t e = mm::launch_carry_only(st->dt, a, hs);
+    if (e != hipSuccess) return hip_fail(e, "maxmin_stream_push (carry)");
+  }
+  st->cur = 1 - st->cur;
+  st->t += m;
+  if (h_n_out) *h_n_out = nout;
+  return ok();
+}
+
+int64_t maxmin_stream_samples(const maxmin_stream_t* st) { return st ? st->t : -1; }
+
+int maxmin_stream_destroy(maxmin_stream_t* st) {
+  if (!st) return ok();
+  hipDeviceSynchronize();
+  hipFree(st->carry[0]);
+  hipFree(st->carry[1]);
+  delete st;
+  return ok();
+}
+
+int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int64_t ld_in, int64_t w_rows,
+                     int64_t w_cols, void* d_max, void* d_min, int64_t ld_out, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: unknown dtype %d", dtype);
+  if (w_rows < 1 || w_cols < 1) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: window < 1");
+  if (rows < 0 || cols < 0) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: negative size");
+  if (ld_in < cols) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: ld_in < cols");
+  const int64_t orows = rows - w_rows + 1, oc = cols - w_cols + 1;
+  if (orows <= 0 || oc <= 0) return ok();
+  if (ld_out < oc) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: ld_out < output width");
+  if (!d_in || !d_max || !d_min) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
+    return fail(MAXMIN_EINVAL, "maxmin_filter_2d: pointer not aligned to the element size");
+  if (w_rows > mm::cols_max_window(dtype))
+    return fail(MAXMIN_EUNSUPPORTED, "maxmin_filter_2d: w_rows=%lld above this build's column-pass limit %lld",
+                (long long)w_rows, (long long)mm::cols_max_window(dtype));
+  if ((orows + w_rows - 1) / w_rows > 65535)
+    return fail(MAXMIN_EUNSUPPORTED, "maxmin_filter_2d: too many row blocks for one launch");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* ws = nullptr;
+  int r = get_ws(st, &ws);
+  if (r) return r;
+  const size_t img = (size_t)rows * (size_t)oc * s;
+  if ((r = ensure_tmp(ws, 2 * img))) return r;
+  void* tmax = ws->tmp;
+  void* tmin = (char*)ws->tmp + img;
+  // row pass: every row is a series of `cols` inputs with window w_cols
+  JobArgs a;
+  a.mode = 2;
+  a.in = d_in;
+  a.ld_in = ld_in;
+  a.n = cols;
+  a.w = w_cols;
+  a.omax = tmax;
+  a.omin = tmin;
+  a.ld_out = oc;
+  const int strat = plan_strategy(dtype, cols, w_cols);
+  hipError_t e;
+  if (strat == MAXMIN_STRATEGY_TILE) {
+    a.tpr = mm::tile_count(cols, w_cols);
+    a.ntiles = a.tpr * rows;
+    e = mm::launch_1d(dtype, mm::kStratTile, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratTile)), st);
+  } else {
+    a.tpr = mm::chunk_count(cols, w_cols);
+    a.ntiles = a.tpr * rows;
+    if ((r = ensure_ring(ws, a.ntiles))) return r;
+    a.ring = ws->ring;
+    a.ring_lg = ws->ring_lg;
+    a.ctl = ws->ctl;
+    e = mm::launch_1d(dtype, mm::kStratChunk, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratChunk)), st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (rows)");
+  e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, st);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (columns)");
+  return ok();
+}
+
+// Synchronise `stream` and report whether any look-back wait on it gave up.
+int maxmin_check_stream(void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = st ? hipStreamSynchronize(st) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "maxmin_check_stream");
+  int dev = 0;
+  hipGetDevice(&dev);
+  Workspace* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_ws.find(std::make_pair(dev, st));
+    if (it == g_ws.end()) return ok();
+    ws = it->second;
+  }
+  mm::Ctl c;
+  e = hipMemcpy(&c, ws->ctl, sizeof c, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_check_stream (read)");
+  if (c.err) return fail(MAXMIN_EDEVICE, "a look-back wait on this stream timed out (results invalid)");
+  return ok();
+}
+
+}  // extern "C"

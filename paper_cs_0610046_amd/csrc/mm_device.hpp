@@ -1,0 +1,140 @@
+// Device-side building blocks shared by the gfx950 max-min kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+// ---------------------------------------------------------------- values
+// Identity elements: lo() for a running maximum, hi() for a running minimum.
+template <class T> struct Lim;
+template <> struct Lim<float> {
+  __device__ static float lo() { return -__builtin_huge_valf(); }
+  __device__ static float hi() { return __builtin_huge_valf(); }
+};
+template <> struct Lim<double> {
+  __device__ static double lo() { return -__builtin_huge_val(); }
+  __device__ static double hi() { return __builtin_huge_val(); }
+};
+template <> struct Lim<int32_t> {
+  __device__ static int32_t lo() { return INT32_MIN; }
+  __device__ static int32_t hi() { return INT32_MAX; }
+};
+template <> struct Lim<uint16_t> {
+  __device__ static uint16_t lo() { return 0; }
+  __device__ static uint16_t hi() { return 0xFFFF; }
+};
+
+// Selection only: compare, then pick one operand's bits unchanged.
+template <class T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
+template <class T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------- LDS layout
+// One pad element per 128 bytes: a thread reading V consecutive elements and
+// a wave writing lane-consecutive elements both stay clear of bank conflicts.
+template <class T> struct Pad {
+  static constexpr int sh = sizeof(T) == 8 ? 4 : (sizeof(T) == 4 ? 5 : 6);
+};
+template <class T> __host__ __device__ constexpr int lds_idx(int i) { return i + (i >> Pad<T>::sh); }
+template <class T> __host__ __device__ constexpr int lds_len(int n) { return n + (n >> Pad<T>::sh) + 1; }
+
+// ---------------------------------------------------------------- shuffles
+template <class T> __device__ __forceinline__ T shup(T v, unsigned d, int width) {
+  return __shfl_up(v, d, width);
+}
+template <> __device__ __forceinline__ uint16_t shup<uint16_t>(uint16_t v, unsigned d, int width) {
+  return (uint16_t)__shfl_up((unsigned)v, d, width);
+}
+template <class T> __device__ __forceinline__ T shdn(T v, unsigned d, int width) {
+  return __shfl_down(v, d, width);
+}
+template <> __device__ __forceinline__ uint16_t shdn<uint16_t>(uint16_t v, unsigned d, int width) {
+  return (uint16_t)__shfl_down((unsigned)v, d, width);
+}
+
+// ---------------------------------------------------------------- series
+// One series of the 1-D filter.  Its n elements are the concatenation of two
+// segments: element i is a[i] for i < na, else b[i - na].  A plain call has
+// na = n; a stream push puts its carried samples in `a` and the new chunk in
+// `b`.  Outputs: n_out = max(0, n - w + 1) maxima and minima.  If `carry` is
+// non-null the last min(n, w-1) inputs are also copied there (the next
+// push's carry).
+template <class T> struct Series {
+  const T* a;
+  const T* b;
+  int64_t na;
+  int64_t n;
+  int64_t w;
+  T* omax;
+  T* omin;
+  T* carry;
+};
+
+template <class T> __device__ __forceinline__ T src_at(const Series<T>& s, int64_t i) {
+  return i < s.na ? s.a[i] : s.b[i - s.na];
+}
+
+// ---------------------------------------------------------------- atomics
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent32(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_agent32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T> __device__ __forceinline__ uint64_t to_bits(T v) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(uint64_t, v);
+  else if constexpr (sizeof(T) == 4) return (uint64_t)__builtin_bit_cast(uint32_t, v);
+  else return (uint64_t)__builtin_bit_cast(uint16_t, v);
+}
+template <class T> __device__ __forceinline__ T from_bits(uint64_t b) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, b);
+  else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, (uint32_t)b);
+  else return __builtin_bit_cast(T, (uint16_t)b);
+}
+
+// Per-launch control words in device memory (one set per HIP stream).
+struct Ctl {
+  uint32_t ticket;  // next chunk tile to hand out (in-order tickets)
+  uint32_t done;    // workgroups that have left the persistent loop
+  uint32_t epoch;   // tags this launch's published aggregates
+  uint32_t err;     // non-zero: a look-back wait gave up (never expected)
+};
+
+// Look-back records of the chunk strategy: 2^lg records of 4 words each.
+struct FlagRing {
+  uint64_t* f;
+  uint32_t lg;
+};
+
+// One launch of a 1-D kernel (see JobMode in the kernel source).
+template <class T> struct Job {
+  int mode;
+  Series<T> one;          // single series
+  int64_t ntiles;         // single series and rows: total tiles of the launch
+  const Series<T>* descs; // described series
+  const int64_t* pre;     // S+1 tile prefix sums (entry S = total)
+  int64_t S;
+  const T* in;            // rows: series k = in[k*ld_in .. k*ld_in + n)
+  int64_t ld_in;
+  int64_t n;
+  int64_t w;
+  T* omax;                // rows: outputs of series k at omax/omin + k*ld_out
+  T* omin;
+  int64_t ld_out;
+  int64_t tpr;            // rows: tiles per row
+  FlagRing ring;          // chunk strategy only
+  Ctl* ctl;
+};
+
+}  // namespace mm

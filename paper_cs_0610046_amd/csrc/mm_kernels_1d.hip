@@ -1,0 +1,730 @@
+// gfx950 kernels of the 1-D running max-min filter.
+//
+// Both strategies rest on the block decomposition of van Herk and
+// Gil-Werman (Related Work; Table 1): cut the series into blocks of B
+// consecutive elements; for a window [j, j+w) that starts in block b1 and
+// ends in block b2,
+//     max a[j..j+w) = max( SUF[j], AGG[b1+1 .. b2-1], PRE[j+w-1] )
+// where SUF[j] is the maximum from j to the end of its block, PRE[e] the
+// maximum from the start of e's block to e, and AGG[b] a whole block's
+// maximum (likewise for the minimum).  With B = w this is the classical
+// form (no middle term).  All of it is selection: results are exact.
+//
+// * Tile strategy (w <= 1024).  One workgroup produces kTileOut windows from
+//   the kTileOut + w - 1 inputs they need, staged in LDS.  B is the largest
+//   power of two <= min(w, 512), so w <= 2B and at most one whole block lies
+//   strictly inside any window.  Threads own 8 consecutive positions; a
+//   block spans B/8 lanes of one wavefront, so SUF/PRE need only in-thread
+//   scans plus a lane-group scan (ds_bpermute shuffles) -- no workgroup-wide
+//   scan and no segmented scan.  PRE is written to LDS and read back at
+//   offset w-1 by the thread that owns the window's start.
+//
+// * Chunk strategy (any w, used for w > 1024).  Blocks of exactly w inputs
+//   aligned at the series start, cut into K chunks of C <= 2048.  The
+//   workgroup that owns input chunk (b, k) emits every window that ENDS in
+//   that chunk (the paper's zero-latency view, Section 1, applied to
+//   chunks): PRE comes from its own chunk plus the aggregates of chunks
+//   (b, 0..k-1); SUF comes from re-reading chunk (b-1, k) (w inputs back,
+//   still in cache) plus the aggregates of chunks (b-1, k+1..K-1).  Each
+//   workgroup publishes its chunk's aggregate as soon as it has loaded it,
+//   and only ever waits on the K-1 chunks handed out just before it
+//   (in-order tickets), so progress is guaranteed and every input is read
+//   from HBM once.
+#include <type_traits>
+
+#include "mm_launch.hpp"
+
+namespace mm {
+
+// ------------------------------------------------------------------ helpers
+// XCD-aware static schedule: consecutive workgroup ids land on different
+// XCDs (round robin over 8), so give XCD x the x-th eighth of the tiles, in
+// order.  Neighbouring tiles then share an L2 (tile halos hit in cache).
+__device__ __forceinline__ void xcd_schedule(int64_t ntiles, int64_t& first, int64_t& stride,
+                                             int64_t& end) {
+  const int NX = 8;
+  const int g = blockIdx.x, G = gridDim.x;
+  if (G < NX || ntiles < NX) {
+    first = g;
+    stride = G;
+    end = ntiles;
+    return;
+  }
+  const int x = g % NX, r = g / NX;
+  const int gx = (G - x + NX - 1) / NX;
+  first = ntiles * x / NX + r;
+  stride = gx;
+  end = ntiles * (x + 1) / NX;
+}
+
+// Last k in [0, S-1] with pre[k] <= t, given pre[0] <= t < pre[S]; pre is
+// non-decreasing.  Every wavefront searches independently (64-ary).
+__device__ int64_t find_series(const int64_t* pre, int64_t S, int64_t t) {
+  const int lane = threadIdx.x & 63;
+  int64_t lo = 0, hi = S - 1;
+  while (hi > lo) {
+    const int64_t span = hi - lo;
+    const int64_t step = span < 64 ? 1 : (span + 63) / 64;
+    int64_t idx = lo + (int64_t)lane * step;
+    if (idx > hi) idx = hi;
+    const bool p = pre[idx] <= t;
+    const uint64_t m = __ballot(p);
+    const int L = 63 - __builtin_clzll(m);
+    int64_t nlo = lo + (int64_t)L * step;
+    if (nlo > hi) nlo = hi;
+    int64_t nhi = hi;
+    if (L < 63) {
+      const int64_t c = lo + (int64_t)(L + 1) * step - 1;
+      if (c < nhi) nhi = c;
+    }
+    lo = nlo;
+    hi = nhi;
+  }
+  return lo;
+}
+
+// What one launch works on: a single series, S described series (packed
+// buffer with descriptors and per-strategy tile prefix sums), or `rows`
+// equal-length series at a fixed stride (the row pass of the 2-D filter).
+enum JobMode : int { kJobOne = 0, kJobDescs = 1, kJobRows = 2 };
+
+template <class T>
+__device__ __forceinline__ int64_t job_tiles(const Job<T>& j) {
+  return j.mode == kJobDescs ? j.pre[j.S] : j.ntiles;
+}
+
+// Series of global tile t, its tile index inside the series, and the global
+// index of the series' first tile.
+template <class T>
+__device__ __forceinline__ Series<T> job_series(const Job<T>& j, int64_t t, int64_t& local, int64_t& gbase) {
+  if (j.mode == kJobOne) {
+    local = t;
+    gbase = 0;
+    return j.one;
+  }
+  if (j.mode == kJobDescs) {
+    const int64_t k = find_series(j.pre, j.S, t);
+    gbase = j.pre[k];
+    local = t - gbase;
+    return j.descs[k];
+  }
+  const int64_t k = t / j.tpr;
+  gbase = k * j.tpr;
+  local = t - gbase;
+  Series<T> s;
+  s.a = j.in + k * j.ld_in;
+  s.b = nullptr;
+  s.na = j.n;
+  s.n = j.n;
+  s.w = j.w;
+  s.omax = j.omax + k * j.ld_out;
+  s.omin = j.omin + k * j.ld_out;
+  s.carry = nullptr;
+  return s;
+}
+
+// ============================================================ tile strategy
+template <class T> struct TileLds {
+  T xs[lds_len<T>(kTileOut + (int)kTileMaxW - 1)];  // inputs of the tile
+  T pm[lds_len<T>(kTileOut)];  // PRE (max) at window ends, then staged max outputs
+  T pn[lds_len<T>(kTileOut)];  // PRE (min) at window ends, then staged min outputs
+};
+
+template <class T>
+__device__ void tile_body(const Series<T>& s, int64_t tile, TileLds<T>& sm) {
+  constexpr int NT = kTileThreads, V = kTileV;
+  const int tid = threadIdx.x;
+  const int64_t nout = s.n - s.w + 1;
+  const int64_t q0 = tile * (int64_t)kTileOut;
+  const int cnt = (int)min((int64_t)kTileOut, nout - q0);
+  const int w = (int)s.w;
+  const int L = cnt + w - 1;  // inputs [q0, q0 + L)
+  const int lgB = 31 - __builtin_clz((unsigned)min(w, kTileMaxBlock));
+  const int B = 1 << lgB;
+
+  // stage the inputs (lane-consecutive, coalesced)
+  for (int i = tid; i < L; i += NT) sm.xs[lds_idx<T>(i)] = src_at(s, q0 + i);
+  __syncthreads();
+
+  // SUF of this thread's own window starts (round 0), PRE everywhere
+  T sx[V], sn[V];
+  const int nround = (L + NT * V - 1) / (NT * V);
+  for (int r = 0; r < nround; ++r) {
+    const int p0 = (r * NT + tid) * V;
+    T v[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = sm.xs[lds_idx<T>(min(p0 + i, L - 1))];
+    T px[V], pn[V], ux[V], un[V];
+    px[0] = v[0];
+    pn[0] = v[0];
+#pragma unroll
+    for (int i = 1; i < V; ++i) {
+      const bool start = ((p0 + i) & (B - 1)) == 0;  // a block begins at p0+i
+      px[i] = start ? v[i] : vmax(px[i - 1], v[i]);
+      pn[i] = start ? v[i] : vmin(pn[i - 1], v[i]);
+    }
+    ux[V - 1] = v[V - 1];
+    un[V - 1] = v[V - 1];
+#pragma unroll
+    for (int i = V - 2; i >= 0; --i) {
+      const bool end = ((p0 + i + 1) & (B - 1)) == 0;  // a block ends at p0+i
+      ux[i] = end ? v[i] : vmax(ux[i + 1], v[i]);
+      un[i] = end ? v[i] : vmin(un[i + 1], v[i]);
+    }
+    if (B > V) {
+      // a block spans m = B/V aligned lanes: scan the lane totals inside
+      // each group (prefix for PRE, suffix for SUF), then fold them in
+      const int m = B / V;
+      const int lig = tid & (m - 1);
+      T ipx = px[V - 1], ipn = pn[V - 1], isx = ux[0], isn = un[0];
+      for (int d = 1; d < m; d <<= 1) {
+        const T a = shup(ipx, d, m), b = shup(ipn, d, m);
+        const T c = shdn(isx, d, m), e = shdn(isn, d, m);
+        if (lig >= d) {
+          ipx = vmax(ipx, a);
+          ipn = vmin(ipn, b);
+        }
+        if (lig + d < m) {
+          isx = vmax(isx, c);
+          isn = vmin(isn, e);
+        }
+      }
+      const T cpx = shup(ipx, 1, m), cpn = shup(ipn, 1, m);
+      const T csx = shdn(isx, 1, m), csn = shdn(isn, 1, m);
+      if (lig > 0) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          px[i] = vmax(px[i], cpx);
+          pn[i] = vmin(pn[i], cpn);
+        }
+      }
+      if (lig < m - 1) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          ux[i] = vmax(ux[i], csx);
+          un[i] = vmin(un[i], csn);
+        }
+      }
+    }
+    // PRE at window ends: input position e = q + w - 1 goes to slot q
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int q = p0 + i - (w - 1);
+      if (q >= 0 && q < cnt) {
+        sm.pm[lds_idx<T>(q)] = px[i];
+        sm.pn[lds_idx<T>(q)] = pn[i];
+      }
+    }
+    if (r == 0) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        sx[i] = ux[i];
+        sn[i] = un[i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // window q = [q, q+w): SUF[q], PRE[q+w-1], and the middle block if any
+  T ox[V], on[V];
+  const int qb = tid * V;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int q = qb + i;
+    T rx = sx[i], rn = sn[i];
+    if (q < cnt) {
+      rx = vmax(rx, sm.pm[lds_idx<T>(q)]);
+      rn = vmin(rn, sm.pn[lds_idx<T>(q)]);
+      const int b1 = q >> lgB, b2 = (q + w - 1) >> lgB;
+      if (b2 >= b1 + 2) {
+        // block b1+1 lies inside the window; its aggregate is PRE at its
+        // last position (b1+2)B-1, stored at slot (b1+2)B-w
+        const int mi = ((b1 + 2) << lgB) - w;
+        rx = vmax(rx, sm.pm[lds_idx<T>(mi)]);
+        rn = vmin(rn, sm.pn[lds_idx<T>(mi)]);
+      }
+    }
+    ox[i] = rx;
+    on[i] = rn;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int q = qb + i;
+    if (q < cnt) {
+      sm.pm[lds_idx<T>(q)] = ox[i];
+      sm.pn[lds_idx<T>(q)] = on[i];
+    }
+  }
+  __syncthreads();
+  T* om = s.omax + q0;
+  T* on_ = s.omin + q0;
+  for (int j = tid; j < cnt; j += NT) {
+    om[j] = sm.pm[lds_idx<T>(j)];
+    on_[j] = sm.pn[lds_idx<T>(j)];
+  }
+  // the last tile holds the series' last w-1 inputs: they are the next carry
+  if (s.carry != nullptr && q0 + cnt == nout) {
+    const int64_t cstart = nout;  // = n - (w - 1)
+    for (int64_t i = cstart + tid; i < s.n; i += NT) s.carry[i - cstart] = sm.xs[lds_idx<T>((int)(i - q0))];
+  }
+  __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
+  __shared__ TileLds<T> sm;
+  const int64_t ntiles = job_tiles(job);
+  int64_t first, stride, end;
+  xcd_schedule(ntiles, first, stride, end);
+  for (int64_t t = first; t < end; t += stride) {
+    int64_t local, gbase;
+    const Series<T> s = job_series(job, t, local, gbase);
+    tile_body<T>(s, local, sm);
+  }
+}
+
+// =========================================================== chunk strategy
+template <class T> struct ChunkLds {
+  T xs[lds_len<T>(kChunkMax)];  // own chunk, later the staged max outputs
+  T hs[lds_len<T>(kChunkMax)];  // chunk w back (shifted by one), later min outputs
+  T red[4][kChunkThreads / 64];  // per-wave scan totals
+  T dep[4];                      // PRE-side and SUF-side aggregates from look-back
+};
+
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// Aggregates live in a ring of 2^lg records indexed by the chunk's ticket;
+// the tag mixes the launch epoch with the ring lap, so a record left by an
+// earlier launch or an earlier lap never validates.
+__device__ __forceinline__ uint64_t* ring_slot(const FlagRing& r, int64_t u) {
+  return r.f + 4 * (u & ((int64_t(1) << r.lg) - 1));
+}
+__device__ __forceinline__ uint32_t ring_tag(const FlagRing& r, uint32_t ep, int64_t u) {
+  uint32_t t = ep ^ ((uint32_t)(u >> r.lg) * 0x9E3779B1u);
+  return t ? t : 0x80000000u;
+}
+
+// An aggregate record: 4 x 64-bit words, each (epoch << 32 | 32 payload
+// bits).  Every word validates itself, so no fence orders them; readers
+// and writers use agent-scope atomics, which stay coherent across XCDs.
+template <class T> __device__ void publish(uint64_t* f, T mx, T mn, uint32_t ep) {
+  const uint64_t e = (uint64_t)ep << 32;
+  const uint64_t bx = to_bits(mx), bn = to_bits(mn);
+  st_agent(f + 0, e | (bx & 0xFFFFFFFFull));
+  st_agent(f + 2, e | (bn & 0xFFFFFFFFull));
+  if constexpr (sizeof(T) == 8) {
+    st_agent(f + 1, e | (bx >> 32));
+    st_agent(f + 3, e | (bn >> 32));
+  }
+}
+
+template <class T> __device__ void fetch(const uint64_t* f, uint32_t ep, T& mx, T& mn, Ctl* ctl) {
+  uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  for (uint32_t spins = 0;; ++spins) {
+    w0 = ld_agent(f + 0);
+    w2 = ld_agent(f + 2);
+    bool ok = (uint32_t)(w0 >> 32) == ep && (uint32_t)(w2 >> 32) == ep;
+    if constexpr (sizeof(T) == 8) {
+      w1 = ld_agent(f + 1);
+      w3 = ld_agent(f + 3);
+      ok = ok && (uint32_t)(w1 >> 32) == ep && (uint32_t)(w3 >> 32) == ep;
+    }
+    if (ok) break;
+    if (spins >= kSpinLimit) {  // never expected: flag it for the host and move on
+      st_agent32(&ctl->err, 1u);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  const uint64_t bx = (w0 & 0xFFFFFFFFull) | ((w1 & 0xFFFFFFFFull) << 32);
+  const uint64_t bn = (w2 & 0xFFFFFFFFull) | ((w3 & 0xFFFFFFFFull) << 32);
+  mx = from_bits<T>(bx);
+  mn = from_bits<T>(bn);
+}
+
+// Workgroup scan of two per-thread totals: exclusive prefix of (ax, an) in
+// thread order and exclusive suffix of (bx, bn); also the inclusive total of
+// (ax, an) over the workgroup.
+template <class T>
+__device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, ChunkLds<T>& sm) {
+  constexpr int NW = kChunkThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T ix = ax, in = an, jx = bx, jn = bn;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T a = shup(ix, d, 64), b = shup(in, d, 64), c = shdn(jx, d, 64), e = shdn(jn, d, 64);
+    if (lane >= d) {
+      ix = vmax(ix, a);
+      in = vmin(in, b);
+    }
+    if (lane + d < 64) {
+      jx = vmax(jx, c);
+      jn = vmin(jn, e);
+    }
+  }
+  if (lane == 63) {
+    sm.red[0][wave] = ix;
+    sm.red[1][wave] = in;
+  }
+  if (lane == 0) {
+    sm.red[2][wave] = jx;
+    sm.red[3][wave] = jn;
+  }
+  __syncthreads();
+  T cpx = Lim<T>::lo(), cpn = Lim<T>::hi(), csx = Lim<T>::lo(), csn = Lim<T>::hi();
+  tx = Lim<T>::lo();
+  tn = Lim<T>::hi();
+#pragma unroll
+  for (int v = 0; v < NW; ++v) {
+    const T r0 = sm.red[0][v], r1 = sm.red[1][v], r2 = sm.red[2][v], r3 = sm.red[3][v];
+    tx = vmax(tx, r0);
+    tn = vmin(tn, r1);
+    if (v < wave) {
+      cpx = vmax(cpx, r0);
+      cpn = vmin(cpn, r1);
+    }
+    if (v > wave) {
+      csx = vmax(csx, r2);
+      csn = vmin(csn, r3);
+    }
+  }
+  T ex = shup(ix, 1, 64), en = shup(in, 1, 64), fx = shdn(jx, 1, 64), fn = shdn(jn, 1, 64);
+  if (lane == 0) {
+    ex = Lim<T>::lo();
+    en = Lim<T>::hi();
+  }
+  if (lane == 63) {
+    fx = Lim<T>::lo();
+    fn = Lim<T>::hi();
+  }
+  ax = vmax(cpx, ex);
+  an = vmin(cpn, en);
+  bx = vmax(csx, fx);
+  bn = vmin(csn, fn);
+}
+
+template <class T>
+__device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const FlagRing& ring, uint32_t ep,
+                           ChunkLds<T>& sm, Ctl* ctl) {
+  constexpr int NT = kChunkThreads, V = kChunkV;
+  const int tid = threadIdx.x;
+  const int64_t w = s.w, n = s.n;
+  const int64_t K = (w + kChunkMax - 1) / kChunkMax;
+  const int64_t C = (w + K - 1) / K;
+  const int64_t b = t / K, k = t - b * K;
+  const int64_t p0 = b * w + k * C;  // first input of the owned chunk
+  const int lenfull = (int)min(C, w - k * C);
+  const int len = (int)min((int64_t)lenfull, n - p0);
+  const bool behind = b >= 1;
+
+  for (int i = tid; i < len; i += NT) sm.xs[lds_idx<T>(i)] = src_at(s, p0 + i);
+  if (behind) {
+    // the window ending at p0+r starts at j = p0-w+1+r, inside chunk
+    // (b-1, k) at local index r+1 (or at the next chunk when r+1 == lenfull);
+    // slot r holds a[j].  The whole rest of that chunk is needed even when
+    // this chunk is cut short by the end of the series.
+    for (int i = tid; i + 1 < lenfull; i += NT) sm.hs[lds_idx<T>(i)] = src_at(s, p0 - w + 1 + i);
+  }
+  __syncthreads();
+  if (s.carry != nullptr) {
+    const int64_t cs = n - min(n, w - 1);
+    for (int i = tid; i < len; i += NT)
+      if (p0 + i >= cs) s.carry[p0 + i - cs] = sm.xs[lds_idx<T>(i)];
+  }
+
+  const int r0 = tid * V;
+  T ax[V], an[V], bx[V], bn[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int r = r0 + i;
+    const bool vo = r < len;
+    const T x = sm.xs[lds_idx<T>(vo ? r : 0)];
+    ax[i] = vo ? x : Lim<T>::lo();
+    an[i] = vo ? x : Lim<T>::hi();
+    const bool vb = behind && (r + 1 < lenfull);
+    const T h = sm.hs[lds_idx<T>(vb ? r : 0)];
+    bx[i] = vb ? h : Lim<T>::lo();
+    bn[i] = vb ? h : Lim<T>::hi();
+  }
+#pragma unroll
+  for (int i = 1; i < V; ++i) {
+    ax[i] = vmax(ax[i - 1], ax[i]);
+    an[i] = vmin(an[i - 1], an[i]);
+  }
+#pragma unroll
+  for (int i = V - 2; i >= 0; --i) {
+    bx[i] = vmax(bx[i + 1], bx[i]);
+    bn[i] = vmin(bn[i + 1], bn[i]);
+  }
+  T epx = ax[V - 1], epn = an[V - 1], esx = bx[0], esn = bn[0], tx, tn;
+  wg_scan2<T>(epx, epn, esx, esn, tx, tn, sm);
+  // own chunk's aggregate, for the chunks after this one
+  if (tid == 0) publish<T>(ring_slot(ring, gbase + t), tx, tn, ring_tag(ring, ep, gbase + t));
+
+  const bool has_out = (p0 + len - 1) >= (w - 1);
+  if (has_out && tid < 64) {
+    // look back over the K-1 chunks handed out just before this one:
+    // (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
+    T prx = Lim<T>::lo(), prn = Lim<T>::hi(), sux = Lim<T>::lo(), sun = Lim<T>::hi();
+    for (int64_t base = t - (K - 1); base < t; base += 64) {
+      const int64_t u = base + tid;
+      if (u >= 0 && u < t) {
+        T mx, mn;
+        fetch<T>(ring_slot(ring, gbase + u), ring_tag(ring, ep, gbase + u), mx, mn, ctl);
+        if (u >= t - k) {
+          prx = vmax(prx, mx);
+          prn = vmin(prn, mn);
+        } else {
+          sux = vmax(sux, mx);
+          sun = vmin(sun, mn);
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      prx = vmax(prx, (T)__shfl_xor(prx, d, 64));
+      prn = vmin(prn, (T)__shfl_xor(prn, d, 64));
+      sux = vmax(sux, (T)__shfl_xor(sux, d, 64));
+      sun = vmin(sun, (T)__shfl_xor(sun, d, 64));
+    }
+    if (tid == 0) {
+      sm.dep[0] = prx;
+      sm.dep[1] = prn;
+      sm.dep[2] = sux;
+      sm.dep[3] = sun;
+    }
+  }
+  __syncthreads();
+  if (has_out) {
+    const T prx = vmax(sm.dep[0], epx), prn = vmin(sm.dep[1], epn);
+    const T sux = vmax(sm.dep[2], esx), sun = vmin(sm.dep[3], esn);
+    // stage outputs: window ending at p0+r -> slot r
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int r = r0 + i;
+      if (r < len) {
+        sm.xs[lds_idx<T>(r)] = vmax(vmax(bx[i], sux), vmax(prx, ax[i]));
+        sm.hs[lds_idx<T>(r)] = vmin(vmin(bn[i], sun), vmin(prn, an[i]));
+      }
+    }
+    __syncthreads();
+    const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
+    T* om = s.omax + (p0 - w + 1);
+    T* on = s.omin + (p0 - w + 1);
+    for (int r = rs + tid; r < len; r += NT) {
+      om[r] = sm.xs[lds_idx<T>(r)];
+      on[r] = sm.hs[lds_idx<T>(r)];
+    }
+  }
+  __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
+  __shared__ ChunkLds<T> sm;
+  __shared__ uint32_t s_ticket;
+  Ctl* ctl = job.ctl;
+  const uint32_t ep = ld_agent32(&ctl->epoch);
+  const int64_t ntiles = job_tiles(job);
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = add_agent32(&ctl->ticket, 1u);
+    __syncthreads();
+    const int64_t t = s_ticket;
+    __syncthreads();
+    if (t >= ntiles) break;
+    int64_t local, gbase;
+    const Series<T> s = job_series(job, t, local, gbase);
+    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl);
+  }
+  // the last workgroup out re-arms the control words for the next launch
+  if (threadIdx.x == 0) {
+    const uint32_t d = add_agent32(&ctl->done, 1u);
+    if (d == gridDim.x - 1) {
+      st_agent32(&ctl->ticket, 0u);
+      st_agent32(&ctl->done, 0u);
+      uint32_t e = ep + 1u;
+      if (e == 0u) e = 1u;
+      st_agent32(&ctl->epoch, e);
+    }
+  }
+}
+
+// ================================================================ batched
+// One workgroup: series descriptors, per-strategy tile counts and their
+// exclusive prefix sums (entry S holds the total).
+template <class T>
+__global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int64_t* in_off,
+                                                        const int64_t* wins, const int64_t* out_off,
+                                                        int64_t S, T* d_max, T* d_min, Series<T>* descs,
+                                                        int64_t* pre_tile, int64_t* pre_chunk) {
+  __shared__ int64_t st[1024], sc[1024];
+  const int tid = threadIdx.x, NTH = blockDim.x;
+  const int64_t per = (S + NTH - 1) / NTH;
+  const int64_t k0 = min(S, (int64_t)tid * per), k1 = min(S, k0 + per);
+  int64_t a = 0, c = 0;
+  for (int64_t k = k0; k < k1; ++k) {
+    const int64_t n = in_off[k + 1] - in_off[k], w = wins[k];
+    if (w >= 1 && n > 0) {
+      if (w <= kTileMaxW) a += tile_count(n, w);
+      else c += chunk_count(n, w);
+    }
+  }
+  st[tid] = a;
+  sc[tid] = c;
+  __syncthreads();
+  for (int d = 1; d < NTH; d <<= 1) {
+    const int64_t xa = tid >= d ? st[tid - d] : 0, xc = tid >= d ? sc[tid - d] : 0;
+    __syncthreads();
+    st[tid] += xa;
+    sc[tid] += xc;
+    __syncthreads();
+  }
+  int64_t ra = st[tid] - a, rc = sc[tid] - c;  // exclusive
+  for (int64_t k = k0; k < k1; ++k) {
+    const int64_t n = in_off[k + 1] - in_off[k], w = wins[k];
+    Series<T> d;
+    d.a = d_in + in_off[k];
+    d.b = nullptr;
+    d.na = n;
+    d.n = n;
+    d.w = w;
+    d.omax = d_max + out_off[k];
+    d.omin = d_min + out_off[k];
+    d.carry = nullptr;
+    descs[k] = d;
+    pre_tile[k] = ra;
+    pre_chunk[k] = rc;
+    if (w >= 1 && n > 0) {
+      if (w <= kTileMaxW) ra += tile_count(n, w);
+      else rc += chunk_count(n, w);
+    }
+  }
+  if (tid == NTH - 1) {
+    pre_tile[S] = st[NTH - 1];
+    pre_chunk[S] = sc[NTH - 1];
+  }
+}
+
+// A push that completes no window: the new carry is simply the last
+// min(n, w-1) samples of (carry ++ chunk).
+template <class T> __global__ void k_carry_only(Series<T> s) {
+  const int64_t keep = min(s.n, s.w - 1);
+  const int64_t cs = s.n - keep;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < keep; i += (int64_t)gridDim.x * blockDim.x)
+    s.carry[i] = src_at(s, cs + i);
+}
+
+// ================================================================ launchers
+template <class F> static hipError_t dispatch(int dtype, F&& f) {
+  switch (dtype) {
+    case 0: return f((float*)nullptr);
+    case 1: return f((double*)nullptr);
+    case 2: return f((int32_t*)nullptr);
+    case 3: return f((uint16_t*)nullptr);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t series_bytes() { return sizeof(Series<float>); }  // pointer/int64 fields: same for every T
+
+template <class T> static Series<T> make_series(const JobArgs& a) {
+  Series<T> s;
+  s.a = (const T*)a.a;
+  s.b = (const T*)a.b;
+  s.na = a.na;
+  s.n = a.n;
+  s.w = a.w;
+  s.omax = (T*)a.omax;
+  s.omin = (T*)a.omin;
+  s.carry = (T*)a.carry;
+  return s;
+}
+
+template <class T> static Job<T> make_job(const JobArgs& a) {
+  Job<T> j;
+  j.mode = a.mode;
+  j.one = make_series<T>(a);
+  j.ntiles = a.ntiles;
+  j.descs = (const Series<T>*)a.descs;
+  j.pre = a.pre;
+  j.S = a.S;
+  j.in = (const T*)a.in;
+  j.ld_in = a.ld_in;
+  j.n = a.n;
+  j.w = a.w;
+  j.omax = (T*)a.omax;
+  j.omin = (T*)a.omin;
+  j.ld_out = a.ld_out;
+  j.tpr = a.tpr;
+  j.ring.f = a.ring;
+  j.ring.lg = a.ring_lg;
+  j.ctl = a.ctl;
+  return j;
+}
+
+static int cu_count() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+template <class K> static int occupancy_grid(K kernel, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb * cu_count();
+}
+
+int grid_cap(int dtype, int strategy) {
+  static int cap[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  if (dtype < 0 || dtype > 3 || (strategy != kStratTile && strategy != kStratChunk)) return 0;
+  int& c = cap[strategy == kStratChunk][dtype];
+  if (!c) {
+    dispatch(dtype, [&](auto* p) {
+      using T = std::remove_pointer_t<decltype(p)>;
+      c = strategy == kStratTile ? occupancy_grid(k_tile<T>, kTileThreads)
+                                 : occupancy_grid(k_chunk<T>, kChunkThreads);
+      return hipSuccess;
+    });
+  }
+  return c;
+}
+
+hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st) {
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    const Job<T> j = make_job<T>(a);
+    if (strategy == kStratTile)
+      hipLaunchKernelGGL(k_tile<T>, dim3(grid), dim3(kTileThreads), 0, st, j);
+    else
+      hipLaunchKernelGGL(k_chunk<T>, dim3(grid), dim3(kChunkThreads), 0, st, j);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
+                                const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
+                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st) {
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    hipLaunchKernelGGL(k_batched_setup<T>, dim3(1), dim3(1024), 0, st, (const T*)d_in, in_off, wins, out_off, S,
+                       (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st) {
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    hipLaunchKernelGGL(k_carry_only<T>, dim3(8), dim3(256), 0, st, make_series<T>(a));
+    return hipGetLastError();
+  });
+}
+
+}  // namespace mm

@@ -1,0 +1,117 @@
+// gfx950 column pass of the 2-D filter (Section 1: the 1-D filter applied to
+// rows, then to columns).  The row pass is the 1-D kernels' "rows" job; this
+// kernel filters the columns of the row-filtered max image (maxima) and min
+// image (minima).
+//
+// One wavefront owns 64 adjacent columns and one block of w_r output rows
+// (van Herk / Gil-Werman with blocks of exactly w_r rows): walking its own
+// block bottom-up it keeps the suffix maxima/minima of every row in LDS; then
+// walking the next block top-down it keeps the running prefix and emits
+//     out[r0+i] = max(SUF[r0+i], PRE[r0+w_r-1+i]).
+// Each row access is 64 consecutive elements of one image row (coalesced);
+// loads are issued in batches of 8 rows to keep them in flight.
+#include <type_traits>
+
+#include "mm_launch.hpp"
+
+namespace mm {
+
+constexpr int kColBatch = 8;
+
+template <class T>
+__global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* __restrict__ N, int64_t ld_t,
+                                             int64_t rows, int64_t oc, int64_t w, T* __restrict__ omax,
+                                             T* __restrict__ omin, int64_t ld_out) {
+  extern __shared__ unsigned char smem_raw[];
+  T* Sx = reinterpret_cast<T*>(smem_raw);  // [w][64]
+  T* Sn = Sx + 64 * w;
+  const int lane = threadIdx.x;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+  const bool act = c < oc;
+  const int64_t cc = act ? c : 0;
+  const int64_t orows = rows - w + 1;
+  const int64_t r0 = (int64_t)blockIdx.y * w;  // first output row of the block
+  if (r0 >= orows) return;
+  const int64_t nb = min(w, orows - r0);  // outputs of this block
+
+  // own block rows [r0, r0+w), bottom-up: suffix max/min
+  T sx = Lim<T>::lo(), sn = Lim<T>::hi();
+  for (int64_t i0 = w - 1; i0 >= 0; i0 -= kColBatch) {
+    T vx[kColBatch], vn[kColBatch];
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 - u;
+      if (i >= 0) {
+        vx[u] = M[(r0 + i) * ld_t + cc];
+        vn[u] = N[(r0 + i) * ld_t + cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 - u;
+      if (i >= 0) {
+        sx = vmax(sx, vx[u]);
+        sn = vmin(sn, vn[u]);
+        Sx[i * 64 + lane] = sx;
+        Sn[i * 64 + lane] = sn;
+      }
+    }
+  }
+  if (act) {
+    omax[r0 * ld_out + c] = sx;  // window r0 is exactly the block
+    omin[r0 * ld_out + c] = sn;
+  }
+  // next block, top-down: prefix max/min over rows r0+w .. r0+w-1+i
+  T px = Lim<T>::lo(), pn = Lim<T>::hi();
+  for (int64_t i0 = 1; i0 < nb; i0 += kColBatch) {
+    T vx[kColBatch], vn[kColBatch];
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 + u;
+      if (i < nb) {
+        vx[u] = M[(r0 + w - 1 + i) * ld_t + cc];
+        vn[u] = N[(r0 + w - 1 + i) * ld_t + cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 + u;
+      if (i < nb) {
+        px = vmax(px, vx[u]);
+        pn = vmin(pn, vn[u]);
+        if (act) {
+          omax[(r0 + i) * ld_out + c] = vmax(Sx[i * 64 + lane], px);
+          omin[(r0 + i) * ld_out + c] = vmin(Sn[i * 64 + lane], pn);
+        }
+      }
+    }
+  }
+}
+
+int64_t cols_max_window(int dtype) {
+  const int64_t s = dtype == 1 ? 8 : (dtype == 3 ? 2 : 4);
+  return (64 * 1024) / (2 * 64 * s);  // LDS: 2 images x 64 columns x w rows <= 64 KiB
+}
+
+hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
+                       int64_t wr, void* d_max, void* d_min, int64_t ld_out, hipStream_t st) {
+  const int64_t orows = rows - wr + 1;
+  if (orows <= 0 || oc <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((oc + 63) / 64), (unsigned)((orows + wr - 1) / wr));
+  auto go = [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    const size_t lds = (size_t)2 * 64 * wr * sizeof(T);
+    hipLaunchKernelGGL(k_cols<T>, grid, dim3(64), lds, st, (const T*)tmax, (const T*)tmin, ld_t, rows, oc, wr,
+                       (T*)d_max, (T*)d_min, ld_out);
+    return hipGetLastError();
+  };
+  switch (dtype) {
+    case 0: return go((float*)nullptr);
+    case 1: return go((double*)nullptr);
+    case 2: return go((int32_t*)nullptr);
+    case 3: return go((uint16_t*)nullptr);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mm

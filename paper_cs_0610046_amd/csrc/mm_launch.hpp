@@ -1,0 +1,92 @@
+// Host-side launchers of the gfx950 kernels (internal to libmaxmin).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mm_device.hpp"
+
+namespace mm {
+
+// Tile strategy: output tiles of kTileOut windows, each in one workgroup.
+constexpr int kTileThreads = 256;
+constexpr int kTileV = 8;                                   // outputs per thread
+constexpr int kTileOut = kTileThreads * kTileV;             // 2048 outputs per tile
+constexpr int kTileMaxBlock = kTileV * 64;                  // largest block: 64 lanes
+constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 1024: w <= 2 * block size
+
+// Chunk strategy: window-aligned chunks of at most kChunkMax inputs.
+constexpr int kChunkThreads = 256;
+constexpr int kChunkV = 8;
+constexpr int kChunkMax = kChunkThreads * kChunkV;          // 2048
+
+// Batched strategy selection happens on the device with the same rule as the
+// host planner's default: tile for w <= kTileMaxW, chunk otherwise.
+
+__host__ __device__ inline int64_t tile_count(int64_t n, int64_t w) {
+  int64_t no = n - w + 1;
+  return no > 0 ? (no + kTileOut - 1) / kTileOut : 0;
+}
+// Number of chunk tiles covering [0, n) for window w (0 if n < w: no output).
+__host__ __device__ inline int64_t chunk_count(int64_t n, int64_t w) {
+  if (n < w || n <= 0) return 0;
+  int64_t K = (w + kChunkMax - 1) / kChunkMax;
+  int64_t C = (w + K - 1) / K;
+  int64_t last = n - 1;
+  return (last / w) * K + (last % w) / C + 1;
+}
+
+// Type-erased description of a 1-D launch (converted to Job<T> inside).
+struct JobArgs {
+  int mode = 0;  // 0 single series, 1 described series, 2 rows
+  // single series: element i is a[i] (i < na) else b[i - na]
+  const void* a = nullptr;
+  const void* b = nullptr;
+  int64_t na = 0;
+  int64_t n = 0;  // also the row length in mode 2
+  int64_t w = 0;
+  void* omax = nullptr;
+  void* omin = nullptr;
+  void* carry = nullptr;
+  int64_t ntiles = 0;
+  // described series
+  const void* descs = nullptr;
+  const int64_t* pre = nullptr;
+  int64_t S = 0;
+  // rows
+  const void* in = nullptr;
+  int64_t ld_in = 0;
+  int64_t ld_out = 0;
+  int64_t tpr = 0;
+  // chunk strategy look-back state
+  uint64_t* ring = nullptr;
+  uint32_t ring_lg = 0;
+  Ctl* ctl = nullptr;
+};
+
+enum Strategy : int { kStratTile = 1, kStratChunk = 2 };
+
+// Occupancy-derived persistent grid sizes (computed once per device).
+int grid_cap(int dtype, int strategy);
+
+hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st);
+
+// Batched: one workgroup fills S descriptors (bytes: S * series_bytes())
+// and the per-strategy tile prefix sums pre_tile/pre_chunk (S+1 each).
+hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
+                                const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
+                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st);
+
+// A stream push that completes no window: new carry = last min(n, w-1)
+// samples of (a[0..na) ++ b).
+hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st);
+
+size_t series_bytes();
+
+// 2-D column pass over the row-filtered images (rows x oc, leading
+// dimension ld_t): max-filter tmax's columns and min-filter tmin's.
+hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
+                       int64_t wr, void* d_max, void* d_min, int64_t ld_out, hipStream_t st);
+int64_t cols_max_window(int dtype);
+
+}  // namespace mm

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point declared in include/maxmin.h, and its host-only paths (argument
+checks, the out-offsets helper, the planner) behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0610046_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "maxmin.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(maxmin_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_cs_0610046_amd import build
+        build.build()
+    return binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("maxmin_filter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
+              "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+        assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
+
+
+def test_argument_errors_without_gpu(lib):
+    vp = ctypes.c_void_p
+    assert lib.maxmin_filter(0, None, 10, 0, None, None, None) == binding.MAXMIN_EINVAL
+    assert "w=0" in binding.maxmin_last_error()
+    assert lib.maxmin_filter(7, None, 10, 2, None, None, None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_filter(0, None, -1, 2, None, None, None) == binding.MAXMIN_EINVAL
+    # w > n: no output, not an error, nothing touched
+    assert lib.maxmin_filter(0, None, 10, 11, None, None, None) == binding.MAXMIN_OK
+    assert lib.maxmin_filter(0, None, 0, 1, None, None, None) == binding.MAXMIN_OK
+    # work to do but null pointers
+    assert lib.maxmin_filter(0, None, 10, 3, None, None, None) == binding.MAXMIN_EINVAL
+    # misaligned pointer (checked before any device call)
+    assert lib.maxmin_filter(0, vp(0x1002), 10, 3, vp(0x2000), vp(0x3000), None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_filter_batched(0, None, None, None, None, -1, None, None, None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_filter_batched(0, None, None, None, None, 0, None, None, None) == binding.MAXMIN_OK
+    assert lib.maxmin_filter_2d(0, None, 5, 5, 4, 2, 2, None, None, 4, None) == binding.MAXMIN_EINVAL  # ld < cols
+    assert lib.maxmin_filter_2d(0, None, 5, 5, 5, 6, 2, None, None, 4, None) == binding.MAXMIN_OK  # no output
+    assert lib.maxmin_set_strategy(9) == binding.MAXMIN_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.maxmin_stream_create(0, 0, ctypes.byref(h)) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_stream_push(None, None, 4, None, None, None, None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_stream_destroy(None) == binding.MAXMIN_OK
+    assert lib.maxmin_stream_samples(None) == -1
+
+
+def test_out_offsets_matches_oracle(lib):
+    rng = np.random.default_rng(3)
+    lens = rng.integers(0, 50, 200)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    wins = rng.integers(1, 60, 200).astype(np.int64)
+    assert np.array_equal(binding.maxmin_out_offsets(offs, wins), oracle.out_offsets(offs, wins))
+    with pytest.raises(binding.MaxMinError):
+        binding.maxmin_out_offsets(np.array([0, 5, 3], np.int64), np.array([1, 1], np.int64))
+    with pytest.raises(binding.MaxMinError):
+        binding.maxmin_out_offsets(np.array([0, 5], np.int64), np.array([0], np.int64))
+
+
+def test_planner(lib):
+    binding.maxmin_set_strategy(binding.STRATEGY_AUTO)
+    assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_TILE
+    assert binding.maxmin_plan(np.float32, 1 << 20, 1024) == binding.STRATEGY_TILE
+    assert binding.maxmin_plan(np.float32, 1 << 20, 1025) == binding.STRATEGY_CHUNK
+    binding.maxmin_set_strategy(binding.STRATEGY_CHUNK)
+    assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_CHUNK
+    binding.maxmin_set_strategy(binding.STRATEGY_TILE)
+    assert binding.maxmin_plan(np.float32, 1 << 20, 5000) == binding.STRATEGY_CHUNK  # tile cannot
+    binding.maxmin_set_strategy(binding.STRATEGY_AUTO)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.lib()
