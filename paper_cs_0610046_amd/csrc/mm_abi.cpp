@@ -457,9 +457,6 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   if (!d_in || !d_max || !d_min) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: null pointer");
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
     return fail(MAXMIN_EINVAL, "maxmin_filter_2d: pointer not aligned to the element size");
-  if (w_rows > mm::cols_max_window(dtype))
-    return fail(MAXMIN_EUNSUPPORTED, "maxmin_filter_2d: w_rows=%lld above this build's column-pass limit %lld",
-                (long long)w_rows, (long long)mm::cols_max_window(dtype));
   if ((orows + w_rows - 1) / w_rows > 65535)
     return fail(MAXMIN_EUNSUPPORTED, "maxmin_filter_2d: too many row blocks for one launch");
   hipStream_t st = (hipStream_t)stream;
@@ -467,9 +464,12 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   int r = get_ws(st, &ws);
   if (r) return r;
   const size_t img = (size_t)rows * (size_t)oc * s;
-  if ((r = ensure_tmp(ws, 2 * img))) return r;
+  const bool big = w_rows > mm::cols_max_window(dtype);
+  const size_t scr = big ? (size_t)mm::cols_scratch_elems(rows, oc, w_rows) * s : 0;
+  if ((r = ensure_tmp(ws, 2 * img + scr))) return r;
   void* tmax = ws->tmp;
   void* tmin = (char*)ws->tmp + img;
+  void* gscr = big ? (void*)((char*)ws->tmp + 2 * img) : nullptr;
   // row pass: every row is a series of `cols` inputs with window w_cols
   JobArgs a;
   a.mode = 2;
@@ -496,7 +496,7 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
     e = mm::launch_1d(dtype, mm::kStratChunk, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratChunk)), st);
   }
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (rows)");
-  e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, st);
+  e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (columns)");
   return ok();
 }

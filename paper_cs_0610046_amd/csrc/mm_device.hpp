@@ -71,8 +71,18 @@ template <class T> struct Series {
   T* carry;
 };
 
+// Series data always lives in global memory: access it through the global
+// address space so the compiler emits global_* (not flat_*) instructions,
+// which neither take the LDS-aperture check nor count against lgkmcnt.
+template <class T> __device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T> __device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 template <class T> __device__ __forceinline__ T src_at(const Series<T>& s, int64_t i) {
-  return i < s.na ? s.a[i] : s.b[i - s.na];
+  return i < s.na ? gload(s.a + i) : gload(s.b + (i - s.na));
 }
 
 // ---------------------------------------------------------------- atomics

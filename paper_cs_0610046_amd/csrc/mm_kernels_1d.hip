@@ -260,13 +260,13 @@ __device__ void tile_body(const Series<T>& s, int64_t tile, TileLds<T>& sm) {
   T* om = s.omax + q0;
   T* on_ = s.omin + q0;
   for (int j = tid; j < cnt; j += NT) {
-    om[j] = sm.pm[lds_idx<T>(j)];
-    on_[j] = sm.pn[lds_idx<T>(j)];
+    gstore(om + j, sm.pm[lds_idx<T>(j)]);
+    gstore(on_ + j, sm.pn[lds_idx<T>(j)]);
   }
   // the last tile holds the series' last w-1 inputs: they are the next carry
   if (s.carry != nullptr && q0 + cnt == nout) {
     const int64_t cstart = nout;  // = n - (w - 1)
-    for (int64_t i = cstart + tid; i < s.n; i += NT) s.carry[i - cstart] = sm.xs[lds_idx<T>((int)(i - q0))];
+    for (int64_t i = cstart + tid; i < s.n; i += NT) gstore(s.carry + (i - cstart), sm.xs[lds_idx<T>((int)(i - q0))]);
   }
   __syncthreads();
 }
@@ -430,7 +430,7 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   if (s.carry != nullptr) {
     const int64_t cs = n - min(n, w - 1);
     for (int i = tid; i < len; i += NT)
-      if (p0 + i >= cs) s.carry[p0 + i - cs] = sm.xs[lds_idx<T>(i)];
+      if (p0 + i >= cs) gstore(s.carry + (p0 + i - cs), sm.xs[lds_idx<T>(i)]);
   }
 
   const int r0 = tid * V;
@@ -513,8 +513,8 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
     T* om = s.omax + (p0 - w + 1);
     T* on = s.omin + (p0 - w + 1);
     for (int r = rs + tid; r < len; r += NT) {
-      om[r] = sm.xs[lds_idx<T>(r)];
-      on[r] = sm.hs[lds_idx<T>(r)];
+      gstore(om + r, sm.xs[lds_idx<T>(r)]);
+      gstore(on + r, sm.hs[lds_idx<T>(r)]);
     }
   }
   __syncthreads();
@@ -612,7 +612,7 @@ template <class T> __global__ void k_carry_only(Series<T> s) {
   const int64_t keep = min(s.n, s.w - 1);
   const int64_t cs = s.n - keep;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < keep; i += (int64_t)gridDim.x * blockDim.x)
-    s.carry[i] = src_at(s, cs + i);
+    gstore(s.carry + i, src_at(s, cs + i));
 }
 
 // ================================================================ launchers

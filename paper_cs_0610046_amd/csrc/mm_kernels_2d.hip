@@ -18,12 +18,22 @@ namespace mm {
 
 constexpr int kColBatch = 8;
 
-template <class T>
+// The block's suffix values live in LDS when 2 x 64 x w_rows elements fit in
+// 64 KiB (GLOBAL_S = false), else in a global scratch slice owned by this
+// wavefront.  The two are separate instantiations so that each pointer has
+// one address space: an LDS pointer that may also point to global memory
+// becomes a flat pointer, and flat LDS stores whose base register falls
+// below the LDS aperture (as unrolled negative offsets produce) fault.
+template <class T, bool GLOBAL_S>
 __global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* __restrict__ N, int64_t ld_t,
                                              int64_t rows, int64_t oc, int64_t w, T* __restrict__ omax,
-                                             T* __restrict__ omin, int64_t ld_out) {
+                                             T* __restrict__ omin, int64_t ld_out, T* __restrict__ gscratch) {
   extern __shared__ unsigned char smem_raw[];
-  T* Sx = reinterpret_cast<T*>(smem_raw);  // [w][64]
+  T* Sx;
+  if constexpr (GLOBAL_S)
+    Sx = gscratch + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (2 * 64 * w);
+  else
+    Sx = reinterpret_cast<T*>(smem_raw);  // [w][64]
   T* Sn = Sx + 64 * w;
   const int lane = threadIdx.x;
   const int64_t c = (int64_t)blockIdx.x * 64 + lane;
@@ -93,16 +103,25 @@ int64_t cols_max_window(int dtype) {
   return (64 * 1024) / (2 * 64 * s);  // LDS: 2 images x 64 columns x w rows <= 64 KiB
 }
 
+int64_t cols_scratch_elems(int64_t rows, int64_t oc, int64_t wr) {
+  const int64_t orows = rows - wr + 1;
+  if (orows <= 0 || oc <= 0) return 0;
+  return ((oc + 63) / 64) * ((orows + wr - 1) / wr) * 2 * 64 * wr;
+}
+
 hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
-                       int64_t wr, void* d_max, void* d_min, int64_t ld_out, hipStream_t st) {
+                       int64_t wr, void* d_max, void* d_min, int64_t ld_out, void* gscratch, hipStream_t st) {
   const int64_t orows = rows - wr + 1;
   if (orows <= 0 || oc <= 0) return hipSuccess;
   const dim3 grid((unsigned)((oc + 63) / 64), (unsigned)((orows + wr - 1) / wr));
   auto go = [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
-    const size_t lds = (size_t)2 * 64 * wr * sizeof(T);
-    hipLaunchKernelGGL(k_cols<T>, grid, dim3(64), lds, st, (const T*)tmax, (const T*)tmin, ld_t, rows, oc, wr,
-                       (T*)d_max, (T*)d_min, ld_out);
+    if (gscratch)
+      hipLaunchKernelGGL((k_cols<T, true>), grid, dim3(64), 0, st, (const T*)tmax, (const T*)tmin, ld_t, rows, oc,
+                         wr, (T*)d_max, (T*)d_min, ld_out, (T*)gscratch);
+    else
+      hipLaunchKernelGGL((k_cols<T, false>), grid, dim3(64), (size_t)2 * 64 * wr * sizeof(T), st, (const T*)tmax,
+                         (const T*)tmin, ld_t, rows, oc, wr, (T*)d_max, (T*)d_min, ld_out, (T*)nullptr);
     return hipGetLastError();
   };
   switch (dtype) {

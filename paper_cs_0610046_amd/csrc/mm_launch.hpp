@@ -85,8 +85,11 @@ size_t series_bytes();
 
 // 2-D column pass over the row-filtered images (rows x oc, leading
 // dimension ld_t): max-filter tmax's columns and min-filter tmin's.
+// Windows above cols_max_window(dtype) keep their per-block suffixes in a
+// global scratch of cols_scratch_elems(rows, oc, wr) elements (else pass null).
 hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
-                       int64_t wr, void* d_max, void* d_min, int64_t ld_out, hipStream_t st);
+                       int64_t wr, void* d_max, void* d_min, int64_t ld_out, void* gscratch, hipStream_t st);
 int64_t cols_max_window(int dtype);
+int64_t cols_scratch_elems(int64_t rows, int64_t oc, int64_t wr);
 
 }  // namespace mm
