@@ -88,138 +88,212 @@ __device__ int64_t find_series(const int64_t* pre, int64_t S, int64_t t) {
 // equal-length series at a fixed stride (the row pass of the 2-D filter).
 enum JobMode : int { kJobOne = 0, kJobDescs = 1, kJobRows = 2 };
 
-template <class T>
+template <int MODE, class T>
 __device__ __forceinline__ int64_t job_tiles(const Job<T>& j) {
-  return j.mode == kJobDescs ? j.pre[j.S] : j.ntiles;
+  return MODE == kJobDescs ? j.pre[j.S] : j.ntiles;
 }
 
 // Series of global tile t, its tile index inside the series, and the global
 // index of the series' first tile.
-template <class T>
+template <int MODE, class T>
 __device__ __forceinline__ Series<T> job_series(const Job<T>& j, int64_t t, int64_t& local, int64_t& gbase) {
-  if (j.mode == kJobOne) {
+  if constexpr (MODE == kJobOne) {
     local = t;
     gbase = 0;
     return j.one;
-  }
-  if (j.mode == kJobDescs) {
+  } else if constexpr (MODE == kJobDescs) {
     const int64_t k = find_series(j.pre, j.S, t);
     gbase = j.pre[k];
     local = t - gbase;
     return j.descs[k];
+  } else {
+    const int64_t k = t / j.tpr;
+    gbase = k * j.tpr;
+    local = t - gbase;
+    Series<T> s;
+    s.a = j.in + k * j.ld_in;
+    s.b = s.a;  // never read (na = n); not null, which the optimiser would treat as unreachable
+    s.na = j.n;
+    s.n = j.n;
+    s.w = j.w;
+    s.omax = j.omax + k * j.ld_out;
+    s.omin = j.omin + k * j.ld_out;
+    s.carry = nullptr;
+    return s;
   }
-  const int64_t k = t / j.tpr;
-  gbase = k * j.tpr;
-  local = t - gbase;
-  Series<T> s;
-  s.a = j.in + k * j.ld_in;
-  s.b = nullptr;
-  s.na = j.n;
-  s.n = j.n;
-  s.w = j.w;
-  s.omax = j.omax + k * j.ld_out;
-  s.omin = j.omin + k * j.ld_out;
-  s.carry = nullptr;
-  return s;
 }
 
 // ============================================================ tile strategy
 template <class T> struct TileLds {
   T xs[lds_len<T>(kTileOut + (int)kTileMaxW - 1)];  // inputs of the tile
-  T pm[lds_len<T>(kTileOut)];  // PRE (max) at window ends, then staged max outputs
-  T pn[lds_len<T>(kTileOut)];  // PRE (min) at window ends, then staged min outputs
+  T pm[lds_len<T>(kTileOut)];  // PRE (max) at window ends
+  T pn[lds_len<T>(kTileOut)];  // PRE (min) at window ends
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// One tile's raw inputs, held in registers from the moment its loads are
+// issued (while the previous tile is being computed) until they are written
+// to LDS.  Aligned single-segment tiles use 16-byte loads.
+template <class T> struct TileIn {
+  static constexpr int EV = 16 / (int)sizeof(T);  // elements per 16-byte load
+  static constexpr int LMAX = kTileOut + (int)kTileMaxW - 1;
+  static constexpr int NV = (LMAX / EV + kTileThreads - 1) / kTileThreads;  // 16-byte loads per thread
+  static constexpr int NS = (LMAX + kTileThreads - 1) / kTileThreads;       // scalar loads per thread
+  static constexpr int N = NV * EV > NS ? NV * EV : NS;
+  T r[N];
+  T tail;
+  int64_t q0;  // first window of the tile
+  int cnt;     // windows in the tile
+  int L;       // inputs of the tile: [q0, q0 + L)
+  bool vec;
 };
 
 template <class T>
-__device__ void tile_body(const Series<T>& s, int64_t tile, TileLds<T>& sm) {
-  constexpr int NT = kTileThreads, V = kTileV;
+__device__ __forceinline__ void tile_prefetch(const Series<T>& s, int64_t tile, TileIn<T>& in) {
+  constexpr int NT = kTileThreads, EV = TileIn<T>::EV;
   const int tid = threadIdx.x;
   const int64_t nout = s.n - s.w + 1;
-  const int64_t q0 = tile * (int64_t)kTileOut;
-  const int cnt = (int)min((int64_t)kTileOut, nout - q0);
+  in.q0 = tile * (int64_t)kTileOut;
+  in.cnt = (int)min((int64_t)kTileOut, nout - in.q0);
+  in.L = in.cnt + (int)s.w - 1;
+  const T* p = nullptr;
+  if (in.q0 + in.L <= s.na) p = s.a + in.q0;
+  else if (in.q0 >= s.na) p = s.b + (in.q0 - s.na);
+  in.vec = p != nullptr && (((uintptr_t)p) & 15) == 0;
+  if (in.vec) {
+    const int nfull = in.L / EV;
+#pragma unroll
+    for (int j = 0; j < TileIn<T>::NV; ++j) {
+      const int v = tid + j * NT;
+      if (v < nfull) {
+        const u32x4 u = gload((const u32x4*)(p + v * EV));
+        __builtin_memcpy(&in.r[j * EV], &u, 16);
+      }
+    }
+    if (tid < in.L - nfull * EV) in.tail = gload(p + nfull * EV + tid);
+  } else {
+#pragma unroll
+    for (int j = 0; j < TileIn<T>::NS; ++j) {
+      const int i = tid + j * NT;
+      if (i < in.L) in.r[j] = src_at(s, in.q0 + i);
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void tile_stage(const TileIn<T>& in, TileLds<T>& sm) {
+  constexpr int NT = kTileThreads, EV = TileIn<T>::EV;
+  const int tid = threadIdx.x;
+  if (in.vec) {
+    const int nfull = in.L / EV;
+#pragma unroll
+    for (int j = 0; j < TileIn<T>::NV; ++j) {
+      const int v = tid + j * NT;
+      if (v < nfull) {
+#pragma unroll
+        for (int e = 0; e < EV; ++e) sm.xs[lds_idx<T>(v * EV + e)] = in.r[j * EV + e];
+      }
+    }
+    if (tid < in.L - nfull * EV) sm.xs[lds_idx<T>(nfull * EV + tid)] = in.tail;
+  } else {
+#pragma unroll
+    for (int j = 0; j < TileIn<T>::NS; ++j) {
+      const int i = tid + j * NT;
+      if (i < in.L) sm.xs[lds_idx<T>(i)] = in.r[j];
+    }
+  }
+}
+
+// Windows [q0, q0 + cnt) of series s from the inputs staged in sm.xs.
+template <class T>
+__device__ __forceinline__ void tile_compute(const Series<T>& s, int64_t q0, int cnt, int L, TileLds<T>& sm) {
+  constexpr int NT = kTileThreads, V = kTileV;
+  const int tid = threadIdx.x;
   const int w = (int)s.w;
-  const int L = cnt + w - 1;  // inputs [q0, q0 + L)
   const int lgB = 31 - __builtin_clz((unsigned)min(w, kTileMaxBlock));
   const int B = 1 << lgB;
 
-  // stage the inputs (lane-consecutive, coalesced)
-  for (int i = tid; i < L; i += NT) sm.xs[lds_idx<T>(i)] = src_at(s, q0 + i);
-  __syncthreads();
-
-  // SUF of this thread's own window starts (round 0), PRE everywhere
+  // PRE everywhere (written to LDS at the window-end slots), then SUF of
+  // this thread's own window starts (round 0 only, kept in registers).  The
+  // two passes run one after the other to keep few arrays live at once.
   T sx[V], sn[V];
   const int nround = (L + NT * V - 1) / (NT * V);
+  const int m = B > V ? B / V : 1;  // lanes per block
+  const int lig = tid & (m - 1);
   for (int r = 0; r < nround; ++r) {
     const int p0 = (r * NT + tid) * V;
+    // halo rounds: a wavefront whose positions all lie past the inputs has
+    // nothing to do (lane groups never straddle wavefronts)
+    if (r > 0 && ((r * NT + (tid & ~63)) * V) >= L) continue;
     T v[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = sm.xs[lds_idx<T>(min(p0 + i, L - 1))];
-    T px[V], pn[V], ux[V], un[V];
-    px[0] = v[0];
-    pn[0] = v[0];
+    {
+      T px[V], pn[V];
+      px[0] = v[0];
+      pn[0] = v[0];
 #pragma unroll
-    for (int i = 1; i < V; ++i) {
-      const bool start = ((p0 + i) & (B - 1)) == 0;  // a block begins at p0+i
-      px[i] = start ? v[i] : vmax(px[i - 1], v[i]);
-      pn[i] = start ? v[i] : vmin(pn[i - 1], v[i]);
-    }
-    ux[V - 1] = v[V - 1];
-    un[V - 1] = v[V - 1];
-#pragma unroll
-    for (int i = V - 2; i >= 0; --i) {
-      const bool end = ((p0 + i + 1) & (B - 1)) == 0;  // a block ends at p0+i
-      ux[i] = end ? v[i] : vmax(ux[i + 1], v[i]);
-      un[i] = end ? v[i] : vmin(un[i + 1], v[i]);
-    }
-    if (B > V) {
-      // a block spans m = B/V aligned lanes: scan the lane totals inside
-      // each group (prefix for PRE, suffix for SUF), then fold them in
-      const int m = B / V;
-      const int lig = tid & (m - 1);
-      T ipx = px[V - 1], ipn = pn[V - 1], isx = ux[0], isn = un[0];
-      for (int d = 1; d < m; d <<= 1) {
-        const T a = shup(ipx, d, m), b = shup(ipn, d, m);
-        const T c = shdn(isx, d, m), e = shdn(isn, d, m);
-        if (lig >= d) {
-          ipx = vmax(ipx, a);
-          ipn = vmin(ipn, b);
+      for (int i = 1; i < V; ++i) {
+        const bool start = ((p0 + i) & (B - 1)) == 0;  // a block begins at p0+i
+        px[i] = start ? v[i] : vmax(px[i - 1], v[i]);
+        pn[i] = start ? v[i] : vmin(pn[i - 1], v[i]);
+      }
+      if (m > 1) {
+        // a block spans m aligned lanes: exclusive scan of the lane totals
+        T ix = px[V - 1], in = pn[V - 1];
+        for (int d = 1; d < m; d <<= 1) {
+          const T a = shup(ix, d, m), b = shup(in, d, m);
+          if (lig >= d) {
+            ix = vmax(ix, a);
+            in = vmin(in, b);
+          }
         }
-        if (lig + d < m) {
-          isx = vmax(isx, c);
-          isn = vmin(isn, e);
+        const T cx = shup(ix, 1, m), cn = shup(in, 1, m);
+        if (lig > 0) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            px[i] = vmax(px[i], cx);
+            pn[i] = vmin(pn[i], cn);
+          }
         }
       }
-      const T cpx = shup(ipx, 1, m), cpn = shup(ipn, 1, m);
-      const T csx = shdn(isx, 1, m), csn = shdn(isn, 1, m);
-      if (lig > 0) {
+      // PRE at window ends: input position e = q + w - 1 goes to slot q
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          px[i] = vmax(px[i], cpx);
-          pn[i] = vmin(pn[i], cpn);
+      for (int i = 0; i < V; ++i) {
+        const int q = p0 + i - (w - 1);
+        if (q >= 0 && q < cnt) {
+          sm.pm[lds_idx<T>(q)] = px[i];
+          sm.pn[lds_idx<T>(q)] = pn[i];
         }
-      }
-      if (lig < m - 1) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          ux[i] = vmax(ux[i], csx);
-          un[i] = vmin(un[i], csn);
-        }
-      }
-    }
-    // PRE at window ends: input position e = q + w - 1 goes to slot q
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const int q = p0 + i - (w - 1);
-      if (q >= 0 && q < cnt) {
-        sm.pm[lds_idx<T>(q)] = px[i];
-        sm.pn[lds_idx<T>(q)] = pn[i];
       }
     }
     if (r == 0) {
+      sx[V - 1] = v[V - 1];
+      sn[V - 1] = v[V - 1];
 #pragma unroll
-      for (int i = 0; i < V; ++i) {
-        sx[i] = ux[i];
-        sn[i] = un[i];
+      for (int i = V - 2; i >= 0; --i) {
+        const bool end = ((p0 + i + 1) & (B - 1)) == 0;  // a block ends at p0+i
+        sx[i] = end ? v[i] : vmax(sx[i + 1], v[i]);
+        sn[i] = end ? v[i] : vmin(sn[i + 1], v[i]);
+      }
+      if (m > 1) {
+        T jx = sx[0], jn = sn[0];
+        for (int d = 1; d < m; d <<= 1) {
+          const T a = shdn(jx, d, m), b = shdn(jn, d, m);
+          if (lig + d < m) {
+            jx = vmax(jx, a);
+            jn = vmin(jn, b);
+          }
+        }
+        const T cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
+        if (lig < m - 1) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            sx[i] = vmax(sx[i], cx);
+            sn[i] = vmin(sn[i], cn);
+          }
+        }
       }
     }
   }
@@ -247,49 +321,72 @@ __device__ void tile_body(const Series<T>& s, int64_t tile, TileLds<T>& sm) {
     ox[i] = rx;
     on[i] = rn;
   }
-  __syncthreads();
+  // store: 16-byte stores when the outputs are aligned, else one by one
+  T* om = s.omax + q0 + qb;
+  T* on_ = s.omin + q0 + qb;
+  const bool ovec = ((((uintptr_t)(s.omax + q0)) | ((uintptr_t)(s.omin + q0))) & 15) == 0;
+  if (ovec && qb + V <= cnt) {
+    constexpr int NV = V * (int)sizeof(T) / 16, EV = 16 / (int)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < V; ++i) {
-    const int q = qb + i;
-    if (q < cnt) {
-      sm.pm[lds_idx<T>(q)] = ox[i];
-      sm.pn[lds_idx<T>(q)] = on[i];
+    for (int k = 0; k < NV; ++k) {
+      u32x4 ux, un;
+      __builtin_memcpy(&ux, &ox[k * EV], 16);
+      __builtin_memcpy(&un, &on[k * EV], 16);
+      gstore((u32x4*)(om + k * EV), ux);
+      gstore((u32x4*)(on_ + k * EV), un);
     }
-  }
-  __syncthreads();
-  T* om = s.omax + q0;
-  T* on_ = s.omin + q0;
-  for (int j = tid; j < cnt; j += NT) {
-    gstore(om + j, sm.pm[lds_idx<T>(j)]);
-    gstore(on_ + j, sm.pn[lds_idx<T>(j)]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (qb + i < cnt) {
+        gstore(om + i, ox[i]);
+        gstore(on_ + i, on[i]);
+      }
   }
   // the last tile holds the series' last w-1 inputs: they are the next carry
+  const int64_t nout = s.n - s.w + 1;
   if (s.carry != nullptr && q0 + cnt == nout) {
     const int64_t cstart = nout;  // = n - (w - 1)
     for (int64_t i = cstart + tid; i < s.n; i += NT) gstore(s.carry + (i - cstart), sm.xs[lds_idx<T>((int)(i - q0))]);
   }
-  __syncthreads();
 }
 
-template <class T>
+// Persistent, software-pipelined: the loads of the next tile are in flight
+// while the current tile is computed and stored.
+template <int MODE, class T>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
   __shared__ TileLds<T> sm;
-  const int64_t ntiles = job_tiles(job);
+  const int64_t ntiles = job_tiles<MODE>(job);
   int64_t first, stride, end;
   xcd_schedule(ntiles, first, stride, end);
+  if (first >= end) return;
+  TileIn<T> in;
+  int64_t local, gbase;
+  Series<T> s = job_series<MODE>(job, first, local, gbase);
+  tile_prefetch<T>(s, local, in);
   for (int64_t t = first; t < end; t += stride) {
-    int64_t local, gbase;
-    const Series<T> s = job_series(job, t, local, gbase);
-    tile_body<T>(s, local, sm);
+    const Series<T> cur = s;
+    const int64_t q0 = in.q0;
+    const int cnt = in.cnt, L = in.L;
+    tile_stage<T>(in, sm);
+    __syncthreads();
+    const int64_t tn = t + stride;
+    if (tn < end) {
+      s = job_series<MODE>(job, tn, local, gbase);
+      tile_prefetch<T>(s, local, in);
+    }
+    tile_compute<T>(cur, q0, cnt, L, sm);
+    __syncthreads();
   }
 }
 
 // =========================================================== chunk strategy
 template <class T> struct ChunkLds {
-  T xs[lds_len<T>(kChunkMax)];  // own chunk, later the staged max outputs
-  T hs[lds_len<T>(kChunkMax)];  // chunk w back (shifted by one), later min outputs
+  T xs[lds_len<T>(kChunkMax)];   // staged max outputs
+  T hs[lds_len<T>(kChunkMax)];   // staged min outputs
   T red[4][kChunkThreads / 64];  // per-wave scan totals
   T dep[4];                      // PRE-side and SUF-side aggregates from look-back
+  uint32_t ticket;
 };
 
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -404,10 +501,100 @@ __device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, ChunkLds<T>& 
   bn = vmin(csn, fn);
 }
 
+// Per-thread inputs of a chunk tile: own positions p0 + r and the shifted
+// positions p0 - w + 1 + r of the chunk w back, r in [16*tid, 16*tid + 16).
+template <class T>
+__device__ __forceinline__ void chunk_load(const Series<T>& s, int64_t p0, int64_t w, int len, int lenfull, bool behind,
+                                           T (&ax)[kChunkV], T (&an)[kChunkV], T (&bx)[kChunkV], T (&bn)[kChunkV]) {
+  constexpr int V = kChunkV, EV = 16 / (int)sizeof(T);
+  const int r0 = threadIdx.x * V;
+  // fast path: one source segment, both ranges 16-byte aligned, full chunk
+  const T* pa = nullptr;
+  const int64_t lo = behind ? p0 - w : p0;
+  if (p0 + len <= s.na) pa = s.a;
+  else if (lo >= s.na) pa = s.b - s.na;
+  const bool vec = pa != nullptr && len == lenfull && (lenfull % V) == 0 &&
+                   ((((uintptr_t)(pa + p0)) | ((uintptr_t)(pa + lo))) & 15) == 0;
+  if (vec) {
+    T v[V];
+    if (r0 < len) {
+#pragma unroll
+      for (int k = 0; k < V / EV; ++k) {
+        const u32x4 u = gload((const u32x4*)(pa + p0 + r0 + k * EV));
+        __builtin_memcpy(&v[k * EV], &u, 16);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const bool vo = r0 + i < len;
+      ax[i] = vo ? v[i] : Lim<T>::lo();
+      an[i] = vo ? v[i] : Lim<T>::hi();
+    }
+    if (behind) {
+      // aligned load of a[p0-w+r0 .. +V) plus the element after: shift by one
+      T u[V + 1];
+      if (r0 < lenfull) {
+#pragma unroll
+        for (int k = 0; k < V / EV; ++k) {
+          const u32x4 q = gload((const u32x4*)(pa + lo + r0 + k * EV));
+          __builtin_memcpy(&u[k * EV], &q, 16);
+        }
+        u[V] = r0 + V < lenfull ? gload(pa + lo + r0 + V) : u[V - 1];
+      }
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const bool vb = r0 + i + 1 < lenfull;
+        bx[i] = vb ? u[i + 1] : Lim<T>::lo();
+        bn[i] = vb ? u[i + 1] : Lim<T>::hi();
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        bx[i] = Lim<T>::lo();
+        bn[i] = Lim<T>::hi();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int r = r0 + i;
+      const bool vo = r < len;
+      const T x = vo ? src_at(s, p0 + r) : T(0);
+      ax[i] = vo ? x : Lim<T>::lo();
+      an[i] = vo ? x : Lim<T>::hi();
+      const bool vb = behind && (r + 1 < lenfull);
+      const T h = vb ? src_at(s, p0 - w + 1 + r) : T(0);
+      bx[i] = vb ? h : Lim<T>::lo();
+      bn[i] = vb ? h : Lim<T>::hi();
+    }
+  }
+}
+
+// Store staged outputs slots [rs, len) of buf to out[0 ..): lane-consecutive,
+// 16-byte stores between a scalar head and tail.
+template <class T>
+__device__ __forceinline__ void chunk_store(T* out, const T* buf, int rs, int len) {
+  constexpr int NT = kChunkThreads, EV = 16 / (int)sizeof(T);
+  const int tid = threadIdx.x;
+  int a0 = rs;
+  while (a0 < len && (((uintptr_t)(out + a0)) & 15) != 0) ++a0;  // uniform, < EV steps
+  for (int r = rs + tid; r < a0; r += NT) gstore(out + r, buf[lds_idx<T>(r)]);
+  const int nv = (len - a0) / EV;
+  for (int v = tid; v < nv; v += NT) {
+    T e[EV];
+#pragma unroll
+    for (int k = 0; k < EV; ++k) e[k] = buf[lds_idx<T>(a0 + v * EV + k)];
+    u32x4 u;
+    __builtin_memcpy(&u, e, 16);
+    gstore((u32x4*)(out + a0 + v * EV), u);
+  }
+  for (int r = a0 + nv * EV + tid; r < len; r += NT) gstore(out + r, buf[lds_idx<T>(r)]);
+}
+
 template <class T>
 __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const FlagRing& ring, uint32_t ep,
-                           ChunkLds<T>& sm, Ctl* ctl) {
-  constexpr int NT = kChunkThreads, V = kChunkV;
+                           ChunkLds<T>& sm, Ctl* ctl, uint32_t& next) {
+  constexpr int V = kChunkV;
   const int tid = threadIdx.x;
   const int64_t w = s.w, n = s.n;
   const int64_t K = (w + kChunkMax - 1) / kChunkMax;
@@ -417,36 +604,42 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   const int lenfull = (int)min(C, w - k * C);
   const int len = (int)min((int64_t)lenfull, n - p0);
   const bool behind = b >= 1;
+  const bool has_out = (p0 + len - 1) >= (w - 1);
 
-  for (int i = tid; i < len; i += NT) sm.xs[lds_idx<T>(i)] = src_at(s, p0 + i);
-  if (behind) {
-    // the window ending at p0+r starts at j = p0-w+1+r, inside chunk
-    // (b-1, k) at local index r+1 (or at the next chunk when r+1 == lenfull);
-    // slot r holds a[j].  The whole rest of that chunk is needed even when
-    // this chunk is cut short by the end of the series.
-    for (int i = tid; i + 1 < lenfull; i += NT) sm.hs[lds_idx<T>(i)] = src_at(s, p0 - w + 1 + i);
+  T ax[V], an[V], bx[V], bn[V];
+  chunk_load<T>(s, p0, w, len, lenfull, behind, ax, an, bx, bn);
+
+  // first look at the K-1 records this chunk depends on while the loads fly
+  // (lane j of wave 0 reads chunk t-K+1+j); misses are re-read after publish
+  const int64_t u0 = t - (K - 1);
+  T fx = Lim<T>::lo(), fn = Lim<T>::hi();
+  bool fok = true;
+  if (has_out && tid < 64 && K - 1 <= 64) {
+    const int64_t u = u0 + tid;
+    if (u >= 0 && u < t) {
+      const uint64_t* f = ring_slot(ring, gbase + u);
+      const uint32_t tg = ring_tag(ring, ep, gbase + u);
+      const uint64_t w0 = ld_agent(f + 0), w2 = ld_agent(f + 2);
+      uint64_t w1 = 0, w3 = 0;
+      fok = (uint32_t)(w0 >> 32) == tg && (uint32_t)(w2 >> 32) == tg;
+      if constexpr (sizeof(T) == 8) {
+        w1 = ld_agent(f + 1);
+        w3 = ld_agent(f + 3);
+        fok = fok && (uint32_t)(w1 >> 32) == tg && (uint32_t)(w3 >> 32) == tg;
+      }
+      fx = from_bits<T>((w0 & 0xFFFFFFFFull) | ((w1 & 0xFFFFFFFFull) << 32));
+      fn = from_bits<T>((w2 & 0xFFFFFFFFull) | ((w3 & 0xFFFFFFFFull) << 32));
+    }
   }
-  __syncthreads();
+
   if (s.carry != nullptr) {
     const int64_t cs = n - min(n, w - 1);
-    for (int i = tid; i < len; i += NT)
-      if (p0 + i >= cs) gstore(s.carry + (p0 + i - cs), sm.xs[lds_idx<T>(i)]);
+    const int r0 = tid * V;
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (r0 + i < len && p0 + r0 + i >= cs) gstore(s.carry + (p0 + r0 + i - cs), ax[i]);
   }
 
-  const int r0 = tid * V;
-  T ax[V], an[V], bx[V], bn[V];
-#pragma unroll
-  for (int i = 0; i < V; ++i) {
-    const int r = r0 + i;
-    const bool vo = r < len;
-    const T x = sm.xs[lds_idx<T>(vo ? r : 0)];
-    ax[i] = vo ? x : Lim<T>::lo();
-    an[i] = vo ? x : Lim<T>::hi();
-    const bool vb = behind && (r + 1 < lenfull);
-    const T h = sm.hs[lds_idx<T>(vb ? r : 0)];
-    bx[i] = vb ? h : Lim<T>::lo();
-    bn[i] = vb ? h : Lim<T>::hi();
-  }
 #pragma unroll
   for (int i = 1; i < V; ++i) {
     ax[i] = vmax(ax[i - 1], ax[i]);
@@ -462,16 +655,15 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   // own chunk's aggregate, for the chunks after this one
   if (tid == 0) publish<T>(ring_slot(ring, gbase + t), tx, tn, ring_tag(ring, ep, gbase + t));
 
-  const bool has_out = (p0 + len - 1) >= (w - 1);
   if (has_out && tid < 64) {
-    // look back over the K-1 chunks handed out just before this one:
     // (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
     T prx = Lim<T>::lo(), prn = Lim<T>::hi(), sux = Lim<T>::lo(), sun = Lim<T>::hi();
-    for (int64_t base = t - (K - 1); base < t; base += 64) {
+    for (int64_t base = u0; base < t; base += 64) {
       const int64_t u = base + tid;
       if (u >= 0 && u < t) {
-        T mx, mn;
-        fetch<T>(ring_slot(ring, gbase + u), ring_tag(ring, ep, gbase + u), mx, mn, ctl);
+        T mx = fx, mn = fn;
+        if (!(base == u0 && K - 1 <= 64 && fok))
+          fetch<T>(ring_slot(ring, gbase + u), ring_tag(ring, ep, gbase + u), mx, mn, ctl);
         if (u >= t - k) {
           prx = vmax(prx, mx);
           prn = vmin(prn, mn);
@@ -495,11 +687,16 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
       sm.dep[3] = sun;
     }
   }
+  // Take the next ticket only now that this chunk waits on nothing: a ticket
+  // taken earlier would sit unpublished behind this chunk's look-back and
+  // stall the chunks that depend on it.  Its latency hides behind the stores.
+  if (tid == 0) next = add_agent32(&ctl->ticket, 1u);
   __syncthreads();
   if (has_out) {
     const T prx = vmax(sm.dep[0], epx), prn = vmin(sm.dep[1], epn);
     const T sux = vmax(sm.dep[2], esx), sun = vmin(sm.dep[3], esn);
     // stage outputs: window ending at p0+r -> slot r
+    const int r0 = tid * V;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       const int r = r0 + i;
@@ -510,32 +707,29 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
     }
     __syncthreads();
     const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
-    T* om = s.omax + (p0 - w + 1);
-    T* on = s.omin + (p0 - w + 1);
-    for (int r = rs + tid; r < len; r += NT) {
-      gstore(om + r, sm.xs[lds_idx<T>(r)]);
-      gstore(on + r, sm.hs[lds_idx<T>(r)]);
-    }
+    chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+    chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
   }
   __syncthreads();
 }
 
-template <class T>
+template <int MODE, class T>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   __shared__ ChunkLds<T> sm;
-  __shared__ uint32_t s_ticket;
   Ctl* ctl = job.ctl;
   const uint32_t ep = ld_agent32(&ctl->epoch);
-  const int64_t ntiles = job_tiles(job);
+  const int64_t ntiles = job_tiles<MODE>(job);
+  // thread 0 takes each next ticket while the current chunk stores its outputs
+  uint32_t next = 0;
+  if (threadIdx.x == 0) next = add_agent32(&ctl->ticket, 1u);
   for (;;) {
-    if (threadIdx.x == 0) s_ticket = add_agent32(&ctl->ticket, 1u);
+    if (threadIdx.x == 0) sm.ticket = next;
     __syncthreads();
-    const int64_t t = s_ticket;
-    __syncthreads();
+    const int64_t t = sm.ticket;
     if (t >= ntiles) break;
     int64_t local, gbase;
-    const Series<T> s = job_series(job, t, local, gbase);
-    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl);
+    const Series<T> s = job_series<MODE>(job, t, local, gbase);
+    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl, next);
   }
   // the last workgroup out re-arms the control words for the next launch
   if (threadIdx.x == 0) {
@@ -688,8 +882,8 @@ int grid_cap(int dtype, int strategy) {
   if (!c) {
     dispatch(dtype, [&](auto* p) {
       using T = std::remove_pointer_t<decltype(p)>;
-      c = strategy == kStratTile ? occupancy_grid(k_tile<T>, kTileThreads)
-                                 : occupancy_grid(k_chunk<T>, kChunkThreads);
+      c = strategy == kStratTile ? occupancy_grid(k_tile<kJobDescs, T>, kTileThreads)
+                                 : occupancy_grid(k_chunk<kJobDescs, T>, kChunkThreads);
       return hipSuccess;
     });
   }
@@ -700,10 +894,16 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
   return dispatch(dtype, [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
     const Job<T> j = make_job<T>(a);
-    if (strategy == kStratTile)
-      hipLaunchKernelGGL(k_tile<T>, dim3(grid), dim3(kTileThreads), 0, st, j);
-    else
-      hipLaunchKernelGGL(k_chunk<T>, dim3(grid), dim3(kChunkThreads), 0, st, j);
+    const dim3 g(grid);
+    if (strategy == kStratTile) {
+      if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T>), g, dim3(kTileThreads), 0, st, j);
+      else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_tile<kJobDescs, T>), g, dim3(kTileThreads), 0, st, j);
+      else hipLaunchKernelGGL((k_tile<kJobRows, T>), g, dim3(kTileThreads), 0, st, j);
+    } else {
+      if (a.mode == kJobOne) hipLaunchKernelGGL((k_chunk<kJobOne, T>), g, dim3(kChunkThreads), 0, st, j);
+      else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_chunk<kJobDescs, T>), g, dim3(kChunkThreads), 0, st, j);
+      else hipLaunchKernelGGL((k_chunk<kJobRows, T>), g, dim3(kChunkThreads), 0, st, j);
+    }
     return hipGetLastError();
   });
 }

@@ -17,8 +17,8 @@ constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 1024: w <= 2 * bl
 
 // Chunk strategy: window-aligned chunks of at most kChunkMax inputs.
 constexpr int kChunkThreads = 256;
-constexpr int kChunkV = 8;
-constexpr int kChunkMax = kChunkThreads * kChunkV;          // 2048
+constexpr int kChunkV = 16;
+constexpr int kChunkMax = kChunkThreads * kChunkV;          // 4096
 
 // Batched strategy selection happens on the device with the same rule as the
 // host planner's default: tile for w <= kTileMaxW, chunk otherwise.
