@@ -214,8 +214,10 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
   const int strat = plan_strategy(dt, a.n, a.w);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
-    a.ntiles = mm::tile_count(a.n, a.w);
-    const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratTile));
+    const int cap = mm::grid_cap(dt, mm::kStratTile);
+    a.run = mm::run_length(a.n - a.w + 1, cap);
+    a.ntiles = mm::run_count(a.n, a.w, a.run);
+    const int grid = (int)std::min<int64_t>(a.ntiles, cap);
     e = mm::launch_1d(dt, mm::kStratTile, a, grid, st);
   } else {
     Workspace* ws = nullptr;
@@ -331,6 +333,7 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
     a.descs = ws->descs;
     a.S = S;
     a.pre = pre_tile;
+    a.run = mm::kRunBatched;
     e = mm::launch_1d(dtype, mm::kStratTile, a, mm::grid_cap(dtype, mm::kStratTile), st);
     if (e != hipSuccess) return e;
     a.pre = pre_chunk;
@@ -483,7 +486,8 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   const int strat = plan_strategy(dtype, cols, w_cols);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
-    a.tpr = mm::tile_count(cols, w_cols);
+    a.run = mm::kRunBatched;
+    a.tpr = mm::run_count(cols, w_cols, a.run);
     a.ntiles = a.tpr * rows;
     e = mm::launch_1d(dtype, mm::kStratTile, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratTile)), st);
   } else {

@@ -143,6 +143,7 @@ template <class T> struct Job {
   T* omin;
   int64_t ld_out;
   int64_t tpr;            // rows: tiles per row
+  int64_t run;            // tile strategy: windows per run (a multiple of the sub-tile)
   FlagRing ring;          // chunk strategy only
   Ctl* ctl;
 };

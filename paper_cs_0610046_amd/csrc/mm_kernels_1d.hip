@@ -124,120 +124,84 @@ __device__ __forceinline__ Series<T> job_series(const Job<T>& j, int64_t t, int6
 }
 
 // ============================================================ tile strategy
-template <class T> struct TileLds {
-  T xs[lds_len<T>(kTileOut + (int)kTileMaxW - 1)];  // inputs of the tile
-  T pm[lds_len<T>(kTileOut)];  // PRE (max) at window ends
-  T pn[lds_len<T>(kTileOut)];  // PRE (min) at window ends
-};
-
+// A workgroup streams through a run of consecutive windows [R0, R1), one
+// sub-tile of kTileOut positions at a time.  Every thread owns 8 consecutive
+// positions of the sub-tile and loads them straight into registers (16-byte
+// loads when aligned; the next sub-tile's loads are issued before the
+// current one is computed).  For sub-tile P_k it computes
+//   PRE over P_k (written to an LDS ring of two sub-tiles), and
+//   SUF over P_k (kept in registers until the next sub-tile),
+// then emits the windows that START in P_{k-1}: their ends lie in P_{k-1} or
+// P_k (w - 1 <= kTileOut), whose PRE values are both in the ring.  Each input
+// is read from memory once; only a run's last sub-tile overlaps the next run.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// One tile's raw inputs, held in registers from the moment its loads are
-// issued (while the previous tile is being computed) until they are written
-// to LDS.  Aligned single-segment tiles use 16-byte loads.
-template <class T> struct TileIn {
-  static constexpr int EV = 16 / (int)sizeof(T);  // elements per 16-byte load
-  static constexpr int LMAX = kTileOut + (int)kTileMaxW - 1;
-  static constexpr int NV = (LMAX / EV + kTileThreads - 1) / kTileThreads;  // 16-byte loads per thread
-  static constexpr int NS = (LMAX + kTileThreads - 1) / kTileThreads;       // scalar loads per thread
-  static constexpr int N = NV * EV > NS ? NV * EV : NS;
-  T r[N];
-  T tail;
-  int64_t q0;  // first window of the tile
-  int cnt;     // windows in the tile
-  int L;       // inputs of the tile: [q0, q0 + L)
-  bool vec;
+template <class T> struct TileLds {
+  T pm[lds_len<T>(2 * kTileOut)];  // PRE (max) ring, indexed by position mod 2*kTileOut
+  T pn[lds_len<T>(2 * kTileOut)];  // PRE (min) ring
 };
 
+// Load the 8 inputs at positions p .. p+7 (those >= lim read as 0, never used).
 template <class T>
-__device__ __forceinline__ void tile_prefetch(const Series<T>& s, int64_t tile, TileIn<T>& in) {
-  constexpr int NT = kTileThreads, EV = TileIn<T>::EV;
-  const int tid = threadIdx.x;
-  const int64_t nout = s.n - s.w + 1;
-  in.q0 = tile * (int64_t)kTileOut;
-  in.cnt = (int)min((int64_t)kTileOut, nout - in.q0);
-  in.L = in.cnt + (int)s.w - 1;
-  const T* p = nullptr;
-  if (in.q0 + in.L <= s.na) p = s.a + in.q0;
-  else if (in.q0 >= s.na) p = s.b + (in.q0 - s.na);
-  in.vec = p != nullptr && (((uintptr_t)p) & 15) == 0;
-  if (in.vec) {
-    const int nfull = in.L / EV;
+__device__ __forceinline__ void run_load(const Series<T>& s, const T* vbase, int64_t p, int64_t lim,
+                                         T (&v)[kTileV]) {
+  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
+  if (vbase != nullptr && p + V <= lim) {
 #pragma unroll
-    for (int j = 0; j < TileIn<T>::NV; ++j) {
-      const int v = tid + j * NT;
-      if (v < nfull) {
-        const u32x4 u = gload((const u32x4*)(p + v * EV));
-        __builtin_memcpy(&in.r[j * EV], &u, 16);
-      }
+    for (int k = 0; k < V / EV; ++k) {
+      const u32x4 u = gload((const u32x4*)(vbase + p + k * EV));
+      __builtin_memcpy(&v[k * EV], &u, 16);
     }
-    if (tid < in.L - nfull * EV) in.tail = gload(p + nfull * EV + tid);
   } else {
 #pragma unroll
-    for (int j = 0; j < TileIn<T>::NS; ++j) {
-      const int i = tid + j * NT;
-      if (i < in.L) in.r[j] = src_at(s, in.q0 + i);
-    }
+    for (int i = 0; i < V; ++i) v[i] = (p + i < lim) ? src_at(s, p + i) : T(0);
   }
 }
 
 template <class T>
-__device__ __forceinline__ void tile_stage(const TileIn<T>& in, TileLds<T>& sm) {
-  constexpr int NT = kTileThreads, EV = TileIn<T>::EV;
-  const int tid = threadIdx.x;
-  if (in.vec) {
-    const int nfull = in.L / EV;
-#pragma unroll
-    for (int j = 0; j < TileIn<T>::NV; ++j) {
-      const int v = tid + j * NT;
-      if (v < nfull) {
-#pragma unroll
-        for (int e = 0; e < EV; ++e) sm.xs[lds_idx<T>(v * EV + e)] = in.r[j * EV + e];
-      }
-    }
-    if (tid < in.L - nfull * EV) sm.xs[lds_idx<T>(nfull * EV + tid)] = in.tail;
-  } else {
-#pragma unroll
-    for (int j = 0; j < TileIn<T>::NS; ++j) {
-      const int i = tid + j * NT;
-      if (i < in.L) sm.xs[lds_idx<T>(i)] = in.r[j];
-    }
-  }
-}
-
-// Windows [q0, q0 + cnt) of series s from the inputs staged in sm.xs.
-template <class T>
-__device__ __forceinline__ void tile_compute(const Series<T>& s, int64_t q0, int cnt, int L, TileLds<T>& sm) {
-  constexpr int NT = kTileThreads, V = kTileV;
+__device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t R1, TileLds<T>& sm) {
+  constexpr int NT = kTileThreads, V = kTileV, TT = kTileOut, RING = 2 * kTileOut;
   const int tid = threadIdx.x;
   const int w = (int)s.w;
   const int lgB = 31 - __builtin_clz((unsigned)min(w, kTileMaxBlock));
   const int B = 1 << lgB;
-
-  // PRE everywhere (written to LDS at the window-end slots), then SUF of
-  // this thread's own window starts (round 0 only, kept in registers).  The
-  // two passes run one after the other to keep few arrays live at once.
-  T sx[V], sn[V];
-  const int nround = (L + NT * V - 1) / (NT * V);
   const int m = B > V ? B / V : 1;  // lanes per block
   const int lig = tid & (m - 1);
-  for (int r = 0; r < nround; ++r) {
-    const int p0 = (r * NT + tid) * V;
-    // halo rounds: a wavefront whose positions all lie past the inputs has
-    // nothing to do (lane groups never straddle wavefronts)
-    if (r > 0 && ((r * NT + (tid & ~63)) * V) >= L) continue;
-    T v[V];
+  const int64_t nout = s.n - s.w + 1;
+  const int64_t lim = min(s.n, R1 + (int64_t)w - 1);  // inputs used: [R0, lim)
+  const int nsub = (int)((R1 - 1 - R0) / TT) + 2;     // sub-tiles P_0 .. P_{nsub-1}
+  // 16-byte loads when [R0, lim) lies in one aligned source segment
+  const T* vbase = nullptr;
+  if (lim <= s.na) vbase = s.a;
+  else if (R0 >= s.na) vbase = s.b - s.na;
+  if (vbase != nullptr && ((((uintptr_t)(vbase + R0)) & 15) != 0)) vbase = nullptr;
+  const bool ovec = ((((uintptr_t)(s.omax + R0)) | ((uintptr_t)(s.omin + R0))) & 15) == 0;
+  const bool last_run = R1 == nout;
+
+  T cur[V], nxt[V];
+  T sx[V], sn[V];  // SUF of the previous sub-tile's positions
+  run_load<T>(s, vbase, R0 + tid * V, lim, cur);
+  for (int k = 0; k < nsub; ++k) {
+    const int pr0 = k * TT + tid * V;  // position of cur[0], relative to R0
+    if (k + 1 < nsub) run_load<T>(s, vbase, R0 + pr0 + TT, lim, nxt);
+    if (s.carry != nullptr && last_run) {
+      // the series' last w-1 inputs are the next push's carry
 #pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = sm.xs[lds_idx<T>(min(p0 + i, L - 1))];
+      for (int i = 0; i < V; ++i) {
+        const int64_t p = R0 + pr0 + i;
+        if (p >= nout && p < s.n) gstore(s.carry + (p - nout), cur[i]);
+      }
+    }
+    // PRE of P_k into the ring
     {
       T px[V], pn[V];
-      px[0] = v[0];
-      pn[0] = v[0];
+      px[0] = cur[0];
+      pn[0] = cur[0];
 #pragma unroll
       for (int i = 1; i < V; ++i) {
-        const bool start = ((p0 + i) & (B - 1)) == 0;  // a block begins at p0+i
-        px[i] = start ? v[i] : vmax(px[i - 1], v[i]);
-        pn[i] = start ? v[i] : vmin(pn[i - 1], v[i]);
+        const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
+        px[i] = start ? cur[i] : vmax(px[i - 1], cur[i]);
+        pn[i] = start ? cur[i] : vmin(pn[i - 1], cur[i]);
       }
       if (m > 1) {
         // a block spans m aligned lanes: exclusive scan of the lane totals
@@ -258,125 +222,106 @@ __device__ __forceinline__ void tile_compute(const Series<T>& s, int64_t q0, int
           }
         }
       }
-      // PRE at window ends: input position e = q + w - 1 goes to slot q
+      const int slot = pr0 & (RING - 1);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        const int q = p0 + i - (w - 1);
-        if (q >= 0 && q < cnt) {
-          sm.pm[lds_idx<T>(q)] = px[i];
-          sm.pn[lds_idx<T>(q)] = pn[i];
+        sm.pm[lds_idx<T>(slot + i)] = px[i];
+        sm.pn[lds_idx<T>(slot + i)] = pn[i];
+      }
+    }
+    // SUF of P_k, kept for the next sub-tile's outputs
+    T ux[V], un[V];
+    ux[V - 1] = cur[V - 1];
+    un[V - 1] = cur[V - 1];
+#pragma unroll
+    for (int i = V - 2; i >= 0; --i) {
+      const bool end = ((pr0 + i + 1) & (B - 1)) == 0;  // a block ends here
+      ux[i] = end ? cur[i] : vmax(ux[i + 1], cur[i]);
+      un[i] = end ? cur[i] : vmin(un[i + 1], cur[i]);
+    }
+    if (m > 1) {
+      T jx = ux[0], jn = un[0];
+      for (int d = 1; d < m; d <<= 1) {
+        const T a = shdn(jx, d, m), b = shdn(jn, d, m);
+        if (lig + d < m) {
+          jx = vmax(jx, a);
+          jn = vmin(jn, b);
+        }
+      }
+      const T cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
+      if (lig < m - 1) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          ux[i] = vmax(ux[i], cx);
+          un[i] = vmin(un[i], cn);
         }
       }
     }
-    if (r == 0) {
-      sx[V - 1] = v[V - 1];
-      sn[V - 1] = v[V - 1];
+    __syncthreads();  // PRE of P_k visible
+    if (k > 0) {
+      // windows starting in P_{k-1}: SUF (registers), PRE at the window end
+      // and the whole block strictly inside, if any (both from the ring)
+      const int qr0 = pr0 - TT;
+      T ox[V], on[V];
 #pragma unroll
-      for (int i = V - 2; i >= 0; --i) {
-        const bool end = ((p0 + i + 1) & (B - 1)) == 0;  // a block ends at p0+i
-        sx[i] = end ? v[i] : vmax(sx[i + 1], v[i]);
-        sn[i] = end ? v[i] : vmin(sn[i + 1], v[i]);
+      for (int i = 0; i < V; ++i) {
+        const int q = qr0 + i, e = q + w - 1;
+        T rx = vmax(sx[i], sm.pm[lds_idx<T>(e & (RING - 1))]);
+        T rn = vmin(sn[i], sm.pn[lds_idx<T>(e & (RING - 1))]);
+        const int b1 = q >> lgB, b2 = e >> lgB;
+        if (b2 >= b1 + 2) {
+          const int mi = (((b1 + 2) << lgB) - 1) & (RING - 1);
+          rx = vmax(rx, sm.pm[lds_idx<T>(mi)]);
+          rn = vmin(rn, sm.pn[lds_idx<T>(mi)]);
+        }
+        ox[i] = rx;
+        on[i] = rn;
       }
-      if (m > 1) {
-        T jx = sx[0], jn = sn[0];
-        for (int d = 1; d < m; d <<= 1) {
-          const T a = shdn(jx, d, m), b = shdn(jn, d, m);
-          if (lig + d < m) {
-            jx = vmax(jx, a);
-            jn = vmin(jn, b);
+      const int64_t q0 = R0 + qr0;
+      T* om = s.omax + q0;
+      T* on_ = s.omin + q0;
+      if (ovec && q0 + V <= R1) {
+        constexpr int NV = V * (int)sizeof(T) / 16, EV = 16 / (int)sizeof(T);
+#pragma unroll
+        for (int k2 = 0; k2 < NV; ++k2) {
+          u32x4 a, b;
+          __builtin_memcpy(&a, &ox[k2 * EV], 16);
+          __builtin_memcpy(&b, &on[k2 * EV], 16);
+          gstore((u32x4*)(om + k2 * EV), a);
+          gstore((u32x4*)(on_ + k2 * EV), b);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          if (q0 + i < R1) {
+            gstore(om + i, ox[i]);
+            gstore(on_ + i, on[i]);
           }
-        }
-        const T cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
-        if (lig < m - 1) {
-#pragma unroll
-          for (int i = 0; i < V; ++i) {
-            sx[i] = vmax(sx[i], cx);
-            sn[i] = vmin(sn[i], cn);
-          }
-        }
       }
     }
-  }
-  __syncthreads();
-
-  // window q = [q, q+w): SUF[q], PRE[q+w-1], and the middle block if any
-  T ox[V], on[V];
-  const int qb = tid * V;
 #pragma unroll
-  for (int i = 0; i < V; ++i) {
-    const int q = qb + i;
-    T rx = sx[i], rn = sn[i];
-    if (q < cnt) {
-      rx = vmax(rx, sm.pm[lds_idx<T>(q)]);
-      rn = vmin(rn, sm.pn[lds_idx<T>(q)]);
-      const int b1 = q >> lgB, b2 = (q + w - 1) >> lgB;
-      if (b2 >= b1 + 2) {
-        // block b1+1 lies inside the window; its aggregate is PRE at its
-        // last position (b1+2)B-1, stored at slot (b1+2)B-w
-        const int mi = ((b1 + 2) << lgB) - w;
-        rx = vmax(rx, sm.pm[lds_idx<T>(mi)]);
-        rn = vmin(rn, sm.pn[lds_idx<T>(mi)]);
-      }
+    for (int i = 0; i < V; ++i) {
+      sx[i] = ux[i];
+      sn[i] = un[i];
+      cur[i] = nxt[i];
     }
-    ox[i] = rx;
-    on[i] = rn;
-  }
-  // store: 16-byte stores when the outputs are aligned, else one by one
-  T* om = s.omax + q0 + qb;
-  T* on_ = s.omin + q0 + qb;
-  const bool ovec = ((((uintptr_t)(s.omax + q0)) | ((uintptr_t)(s.omin + q0))) & 15) == 0;
-  if (ovec && qb + V <= cnt) {
-    constexpr int NV = V * (int)sizeof(T) / 16, EV = 16 / (int)sizeof(T);
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      u32x4 ux, un;
-      __builtin_memcpy(&ux, &ox[k * EV], 16);
-      __builtin_memcpy(&un, &on[k * EV], 16);
-      gstore((u32x4*)(om + k * EV), ux);
-      gstore((u32x4*)(on_ + k * EV), un);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < V; ++i)
-      if (qb + i < cnt) {
-        gstore(om + i, ox[i]);
-        gstore(on_ + i, on[i]);
-      }
-  }
-  // the last tile holds the series' last w-1 inputs: they are the next carry
-  const int64_t nout = s.n - s.w + 1;
-  if (s.carry != nullptr && q0 + cnt == nout) {
-    const int64_t cstart = nout;  // = n - (w - 1)
-    for (int64_t i = cstart + tid; i < s.n; i += NT) gstore(s.carry + (i - cstart), sm.xs[lds_idx<T>((int)(i - q0))]);
+    __syncthreads();  // ring slots of P_{k-1} may now be reused by P_{k+1}
   }
 }
 
-// Persistent, software-pipelined: the loads of the next tile are in flight
-// while the current tile is computed and stored.
+// Persistent: XCD-aware static schedule over runs.
 template <int MODE, class T>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
   __shared__ TileLds<T> sm;
-  const int64_t ntiles = job_tiles<MODE>(job);
+  const int64_t nruns = job_tiles<MODE>(job);
   int64_t first, stride, end;
-  xcd_schedule(ntiles, first, stride, end);
-  if (first >= end) return;
-  TileIn<T> in;
-  int64_t local, gbase;
-  Series<T> s = job_series<MODE>(job, first, local, gbase);
-  tile_prefetch<T>(s, local, in);
+  xcd_schedule(nruns, first, stride, end);
   for (int64_t t = first; t < end; t += stride) {
-    const Series<T> cur = s;
-    const int64_t q0 = in.q0;
-    const int cnt = in.cnt, L = in.L;
-    tile_stage<T>(in, sm);
-    __syncthreads();
-    const int64_t tn = t + stride;
-    if (tn < end) {
-      s = job_series<MODE>(job, tn, local, gbase);
-      tile_prefetch<T>(s, local, in);
-    }
-    tile_compute<T>(cur, q0, cnt, L, sm);
-    __syncthreads();
+    int64_t local, gbase;
+    const Series<T> s = job_series<MODE>(job, t, local, gbase);
+    const int64_t nout = s.n - s.w + 1;
+    const int64_t R0 = local * job.run;
+    run_body<T>(s, R0, min(nout, R0 + job.run), sm);
   }
 }
 
@@ -751,7 +696,7 @@ template <class T>
 __global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int64_t* in_off,
                                                         const int64_t* wins, const int64_t* out_off,
                                                         int64_t S, T* d_max, T* d_min, Series<T>* descs,
-                                                        int64_t* pre_tile, int64_t* pre_chunk) {
+                                                        int64_t* pre_tile, int64_t* pre_chunk, int64_t run) {
   __shared__ int64_t st[1024], sc[1024];
   const int tid = threadIdx.x, NTH = blockDim.x;
   const int64_t per = (S + NTH - 1) / NTH;
@@ -760,7 +705,7 @@ __global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int
   for (int64_t k = k0; k < k1; ++k) {
     const int64_t n = in_off[k + 1] - in_off[k], w = wins[k];
     if (w >= 1 && n > 0) {
-      if (w <= kTileMaxW) a += tile_count(n, w);
+      if (w <= kTileMaxW) a += run_count(n, w, run);
       else c += chunk_count(n, w);
     }
   }
@@ -790,7 +735,7 @@ __global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int
     pre_tile[k] = ra;
     pre_chunk[k] = rc;
     if (w >= 1 && n > 0) {
-      if (w <= kTileMaxW) ra += tile_count(n, w);
+      if (w <= kTileMaxW) ra += run_count(n, w, run);
       else rc += chunk_count(n, w);
     }
   }
@@ -851,6 +796,7 @@ template <class T> static Job<T> make_job(const JobArgs& a) {
   j.omin = (T*)a.omin;
   j.ld_out = a.ld_out;
   j.tpr = a.tpr;
+  j.run = a.run;
   j.ring.f = a.ring;
   j.ring.lg = a.ring_lg;
   j.ctl = a.ctl;
@@ -914,7 +860,7 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
   return dispatch(dtype, [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
     hipLaunchKernelGGL(k_batched_setup<T>, dim3(1), dim3(1024), 0, st, (const T*)d_in, in_off, wins, out_off, S,
-                       (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk);
+                       (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk, (int64_t)kRunBatched);
     return hipGetLastError();
   });
 }

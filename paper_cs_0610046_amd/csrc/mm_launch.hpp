@@ -8,12 +8,14 @@
 
 namespace mm {
 
-// Tile strategy: output tiles of kTileOut windows, each in one workgroup.
+// Tile strategy: a workgroup streams through runs of consecutive windows in
+// sub-tiles of kTileOut positions.
 constexpr int kTileThreads = 256;
-constexpr int kTileV = 8;                                   // outputs per thread
-constexpr int kTileOut = kTileThreads * kTileV;             // 2048 outputs per tile
+constexpr int kTileV = 8;                                   // positions per thread
+constexpr int kTileOut = kTileThreads * kTileV;             // 2048 positions per sub-tile
 constexpr int kTileMaxBlock = kTileV * 64;                  // largest block: 64 lanes
 constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 1024: w <= 2 * block size
+constexpr int64_t kRunBatched = 32 * kTileOut;              // windows per run in batched / rows jobs
 
 // Chunk strategy: window-aligned chunks of at most kChunkMax inputs.
 constexpr int kChunkThreads = 256;
@@ -23,9 +25,17 @@ constexpr int kChunkMax = kChunkThreads * kChunkV;          // 4096
 // Batched strategy selection happens on the device with the same rule as the
 // host planner's default: tile for w <= kTileMaxW, chunk otherwise.
 
-__host__ __device__ inline int64_t tile_count(int64_t n, int64_t w) {
+// Runs of `run` windows covering the n - w + 1 windows of a series.
+__host__ __device__ inline int64_t run_count(int64_t n, int64_t w, int64_t run) {
   int64_t no = n - w + 1;
-  return no > 0 ? (no + kTileOut - 1) / kTileOut : 0;
+  return no > 0 ? (no + run - 1) / run : 0;
+}
+// Run length for a single series on `grid` workgroups: about one run per
+// workgroup, a multiple of the sub-tile.
+inline int64_t run_length(int64_t nout, int64_t grid) {
+  int64_t r = (nout + grid - 1) / grid;
+  r = (r + kTileOut - 1) / kTileOut * kTileOut;
+  return r < kTileOut ? kTileOut : r;
 }
 // Number of chunk tiles covering [0, n) for window w (0 if n < w: no output).
 __host__ __device__ inline int64_t chunk_count(int64_t n, int64_t w) {
@@ -58,6 +68,7 @@ struct JobArgs {
   int64_t ld_in = 0;
   int64_t ld_out = 0;
   int64_t tpr = 0;
+  int64_t run = 0;  // tile strategy: windows per run
   // chunk strategy look-back state
   uint64_t* ring = nullptr;
   uint32_t ring_lg = 0;
