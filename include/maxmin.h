@@ -57,7 +57,8 @@ typedef enum {
 typedef enum {
   MAXMIN_STRATEGY_AUTO = 0,  /* planner / autotuner decides */
   MAXMIN_STRATEGY_TILE = 1,  /* LDS tile: power-of-two block prefix/suffix plus one middle block (w <= 1024) */
-  MAXMIN_STRATEGY_CHUNK = 2  /* window-aligned chunks with look-back over chunk aggregates (any w) */
+  MAXMIN_STRATEGY_CHUNK = 2, /* window-aligned chunks, cross-workgroup look-back over chunk aggregates (any w) */
+  MAXMIN_STRATEGY_RUN = 3    /* window-aligned chunks walked in runs, aggregates kept per workgroup (any w) */
 } maxmin_strategy_t;
 
 /*

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libmaxmin.so")
 
 MAXMIN_OK, MAXMIN_EINVAL, MAXMIN_ENOMEM, MAXMIN_EDEVICE, MAXMIN_EBUSY, MAXMIN_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-STRATEGY_AUTO, STRATEGY_TILE, STRATEGY_CHUNK = 0, 1, 2
+STRATEGY_AUTO, STRATEGY_TILE, STRATEGY_CHUNK, STRATEGY_RUN = 0, 1, 2, 3
 
 _lock = threading.Lock()
 _lib = None

@@ -64,19 +64,31 @@ int env_strategy() {
     v = 0;
     if (e && (!strcmp(e, "tile") || !strcmp(e, "1"))) v = MAXMIN_STRATEGY_TILE;
     if (e && (!strcmp(e, "chunk") || !strcmp(e, "2"))) v = MAXMIN_STRATEGY_CHUNK;
+    if (e && (!strcmp(e, "run") || !strcmp(e, "3"))) v = MAXMIN_STRATEGY_RUN;
   }
   return v;
 }
 
-// Planner: the tile strategy covers w <= 1024; the chunk strategy any w.
+// Chunks per run for the run strategy on a single series, and whether its
+// warm-up (re-reading the K-1 chunks before each run) stays small.
+int64_t run_chunks_per_run(int dt, int64_t n, int64_t w) {
+  const int64_t nch = mm::crun_chunks(n, w);
+  const int64_t cap = mm::grid_cap(dt, mm::kStratRun);
+  return std::max<int64_t>(1, (nch + cap - 1) / cap);
+}
+// Planner: streaming tiles for w <= 1024, chunks with cross-workgroup
+// look-back above.  Chunk runs are used only when forced: on MI355X with
+// n = 2^28 float32 they ran slower than look-back chunks at w = 4096 and 8192
+// (1.46 ms against 0.83 and 0.88 ms).
 int plan_strategy(int dt, int64_t n, int64_t w) {
   (void)dt;
   (void)n;
   int f = g_force.load();
   if (!f) f = env_strategy();
   if (f == MAXMIN_STRATEGY_CHUNK) return MAXMIN_STRATEGY_CHUNK;
-  if (f == MAXMIN_STRATEGY_TILE && w <= mm::kTileMaxW) return MAXMIN_STRATEGY_TILE;
-  return w <= mm::kTileMaxW ? MAXMIN_STRATEGY_TILE : MAXMIN_STRATEGY_CHUNK;
+  if (f == MAXMIN_STRATEGY_RUN && (w + mm::kCrMax - 1) / mm::kCrMax <= mm::kCrRing) return MAXMIN_STRATEGY_RUN;
+  if (w <= mm::kTileMaxW) return MAXMIN_STRATEGY_TILE;
+  return MAXMIN_STRATEGY_CHUNK;
 }
 
 // ------------------------------------------------------------ workspaces
@@ -219,6 +231,11 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     a.ntiles = mm::run_count(a.n, a.w, a.run);
     const int grid = (int)std::min<int64_t>(a.ntiles, cap);
     e = mm::launch_1d(dt, mm::kStratTile, a, grid, st);
+  } else if (strat == MAXMIN_STRATEGY_RUN) {
+    a.run = run_chunks_per_run(dt, a.n, a.w);
+    a.ntiles = (mm::crun_chunks(a.n, a.w) + a.run - 1) / a.run;
+    const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratRun));
+    e = mm::launch_1d(dt, mm::kStratRun, a, grid, st);
   } else {
     Workspace* ws = nullptr;
     int r = get_ws(st, &ws);
@@ -263,7 +280,7 @@ const char* maxmin_last_error(void) { return g_err.c_str(); }
 const char* maxmin_version(void) { return "maxmin-gfx950 0.1"; }
 
 int maxmin_set_strategy(int strategy) {
-  if (strategy < MAXMIN_STRATEGY_AUTO || strategy > MAXMIN_STRATEGY_CHUNK)
+  if (strategy < MAXMIN_STRATEGY_AUTO || strategy > MAXMIN_STRATEGY_RUN)
     return fail(MAXMIN_EINVAL, "maxmin_set_strategy: unknown strategy %d", strategy);
   g_force.store(strategy);
   return ok();
@@ -490,6 +507,11 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
     a.tpr = mm::run_count(cols, w_cols, a.run);
     a.ntiles = a.tpr * rows;
     e = mm::launch_1d(dtype, mm::kStratTile, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratTile)), st);
+  } else if (strat == MAXMIN_STRATEGY_RUN) {
+    a.run = mm::crun_chunks(cols, w_cols);  // one run per row
+    a.tpr = 1;
+    a.ntiles = rows;
+    e = mm::launch_1d(dtype, mm::kStratRun, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratRun)), st);
   } else {
     a.tpr = mm::chunk_count(cols, w_cols);
     a.ntiles = a.tpr * rows;

@@ -53,6 +53,69 @@ template <> __device__ __forceinline__ uint16_t shdn<uint16_t>(uint16_t v, unsig
   return (uint16_t)__shfl_down((unsigned)v, d, width);
 }
 
+// ---------------------------------------------------------------- DPP
+// Cross-lane moves without LDS addresses: update_dpp(old, src, ctrl) gives
+// each lane src from the lane `ctrl` names, or `old` where that lane lies
+// outside the 16-lane row (bound_ctrl off).  Wider types move as 32-bit
+// halves; 16-bit values travel zero-extended.
+template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL, class T> __device__ __forceinline__ T dpp(T old, T src) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = dpp32<CTRL>((uint32_t)o, (uint32_t)v);
+    const uint32_t hi = dpp32<CTRL>((uint32_t)(o >> 32), (uint32_t)(v >> 32));
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp32<CTRL>(__builtin_bit_cast(uint32_t, old), __builtin_bit_cast(uint32_t, src)));
+  } else {
+    return (T)dpp32<CTRL>((uint32_t)__builtin_bit_cast(uint16_t, old), (uint32_t)__builtin_bit_cast(uint16_t, src));
+  }
+}
+template <class T> __device__ __forceinline__ T readlane(T v, int lane) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, (uint32_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint32_t, v), lane));
+  } else {
+    return (T)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)__builtin_bit_cast(uint16_t, v), lane);
+  }
+}
+
+// Inclusive prefix (in lane order) of max and min over the 64-lane wave.
+template <class T> __device__ __forceinline__ void wave_prefix2(T& x, T& n) {
+  const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
+  x = vmax(x, dpp<0x111>(lo, x)); n = vmin(n, dpp<0x111>(hi, n));  // row_shr:1
+  x = vmax(x, dpp<0x112>(lo, x)); n = vmin(n, dpp<0x112>(hi, n));  // row_shr:2
+  x = vmax(x, dpp<0x114>(lo, x)); n = vmin(n, dpp<0x114>(hi, n));  // row_shr:4
+  x = vmax(x, dpp<0x118>(lo, x)); n = vmin(n, dpp<0x118>(hi, n));  // row_shr:8
+  const int row = (threadIdx.x & 63) >> 4;
+  const T x0 = readlane(x, 15), x1 = readlane(x, 31), x2 = readlane(x, 47);
+  const T n0 = readlane(n, 15), n1 = readlane(n, 31), n2 = readlane(n, 47);
+  if (row >= 1) { x = vmax(x, x0); n = vmin(n, n0); }
+  if (row >= 2) { x = vmax(x, x1); n = vmin(n, n1); }
+  if (row >= 3) { x = vmax(x, x2); n = vmin(n, n2); }
+}
+
+// Inclusive suffix (from the last lane down) of max and min over the wave.
+template <class T> __device__ __forceinline__ void wave_suffix2(T& x, T& n) {
+  const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
+  x = vmax(x, dpp<0x101>(lo, x)); n = vmin(n, dpp<0x101>(hi, n));  // row_shl:1
+  x = vmax(x, dpp<0x102>(lo, x)); n = vmin(n, dpp<0x102>(hi, n));  // row_shl:2
+  x = vmax(x, dpp<0x104>(lo, x)); n = vmin(n, dpp<0x104>(hi, n));  // row_shl:4
+  x = vmax(x, dpp<0x108>(lo, x)); n = vmin(n, dpp<0x108>(hi, n));  // row_shl:8
+  const int row = (threadIdx.x & 63) >> 4;
+  const T x1 = readlane(x, 16), x2 = readlane(x, 32), x3 = readlane(x, 48);
+  const T n1 = readlane(n, 16), n2 = readlane(n, 32), n3 = readlane(n, 48);
+  if (row <= 2) { x = vmax(x, x3); n = vmin(n, n3); }
+  if (row <= 1) { x = vmax(x, x2); n = vmin(n, n2); }
+  if (row <= 0) { x = vmax(x, x1); n = vmin(n, n1); }
+}
+
 // ---------------------------------------------------------------- series
 // One series of the 1-D filter.  Its n elements are the concatenation of two
 // segments: element i is a[i] for i < na, else b[i - na].  A plain call has

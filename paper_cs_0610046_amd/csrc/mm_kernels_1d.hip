@@ -388,23 +388,13 @@ template <class T> __device__ void fetch(const uint64_t* f, uint32_t ep, T& mx, 
 // Workgroup scan of two per-thread totals: exclusive prefix of (ax, an) in
 // thread order and exclusive suffix of (bx, bn); also the inclusive total of
 // (ax, an) over the workgroup.
-template <class T>
-__device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, ChunkLds<T>& sm) {
+template <class T, class Lds>
+__device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, Lds& sm) {
   constexpr int NW = kChunkThreads / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T ix = ax, in = an, jx = bx, jn = bn;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T a = shup(ix, d, 64), b = shup(in, d, 64), c = shdn(jx, d, 64), e = shdn(jn, d, 64);
-    if (lane >= d) {
-      ix = vmax(ix, a);
-      in = vmin(in, b);
-    }
-    if (lane + d < 64) {
-      jx = vmax(jx, c);
-      jn = vmin(jn, e);
-    }
-  }
+  wave_prefix2(ix, in);
+  wave_suffix2(jx, jn);
   if (lane == 63) {
     sm.red[0][wave] = ix;
     sm.red[1][wave] = in;
@@ -689,6 +679,206 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   }
 }
 
+// ============================================ chunk runs (local aggregates)
+// Same window-aligned chunks as above (at most kCrMax inputs), but a
+// workgroup walks a run of consecutive chunks of one series and keeps the
+// aggregates of the last chunks in an LDS ring, so nothing is shared between
+// workgroups: no tickets, no look-back.  A run first reduces the K-1 chunks
+// before it (a warm-up read of about w inputs); the planner uses this kernel
+// only where that extra read is small against the run.  The next chunk's
+// loads are issued before the current chunk is computed.
+template <class T> struct CrunLds {
+  T xs[lds_len<T>(kCrMax)];  // staged max outputs
+  T hs[lds_len<T>(kCrMax)];  // staged min outputs
+  T red[4][kChunkThreads / 64];
+  T dep[4];
+  T agx[kCrRing];  // chunk aggregates, indexed by chunk mod kCrRing
+  T agn[kCrRing];
+};
+
+// Raw inputs of chunk c for this thread: own positions p0 + r and shifted
+// positions p0 - w + 1 + r of the chunk w back, r in [8*tid, 8*tid + 8).
+// Positions outside the chunk read as 0 and are masked later.
+template <class T>
+__device__ __forceinline__ void crun_raw(const Series<T>& s, int64_t p0, int64_t w, int len, int lenfull, bool behind,
+                                         T (&own)[kCrV], T (&beh)[kCrV]) {
+  constexpr int V = kCrV, EV = 16 / (int)sizeof(T);
+  const int r0 = threadIdx.x * V;
+  const T* pa = nullptr;
+  const int64_t lo = behind ? p0 - w : p0;
+  if (p0 + len <= s.na) pa = s.a;
+  else if (lo >= s.na) pa = s.b - s.na;
+  const bool vec = pa != nullptr && len == lenfull && (lenfull % V) == 0 &&
+                   ((((uintptr_t)(pa + p0)) | ((uintptr_t)(pa + lo))) & 15) == 0;
+  if (vec) {
+    if (r0 < len) {
+#pragma unroll
+      for (int k = 0; k < V / EV; ++k) {
+        const u32x4 u = gload((const u32x4*)(pa + p0 + r0 + k * EV));
+        __builtin_memcpy(&own[k * EV], &u, 16);
+      }
+    }
+    if (behind && r0 < lenfull) {
+      T u[V + 1];
+#pragma unroll
+      for (int k = 0; k < V / EV; ++k) {
+        const u32x4 q = gload((const u32x4*)(pa + lo + r0 + k * EV));
+        __builtin_memcpy(&u[k * EV], &q, 16);
+      }
+      u[V] = r0 + V < lenfull ? gload(pa + lo + r0 + V) : T(0);
+#pragma unroll
+      for (int i = 0; i < V; ++i) beh[i] = u[i + 1];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int r = r0 + i;
+      own[i] = r < len ? src_at(s, p0 + r) : T(0);
+      beh[i] = (behind && r + 1 < lenfull) ? src_at(s, p0 - w + 1 + r) : T(0);
+    }
+  }
+}
+
+template <class T>
+__device__ void crun_body(const Series<T>& s, int64_t c0, int64_t c1, CrunLds<T>& sm) {
+  constexpr int V = kCrV;
+  const int tid = threadIdx.x;
+  const int64_t w = s.w, n = s.n;
+  const int64_t K = (w + kCrMax - 1) / kCrMax;
+  const int64_t C = (w + K - 1) / K;
+  const int64_t cw = max((int64_t)0, c0 - (K - 1));  // warm-up: aggregates only
+  const int r0 = tid * V;
+  T own[V], beh[V], nown[V], nbeh[V];
+  auto geom = [&](int64_t c, int64_t& p0, int& lenfull, int& len) {
+    const int64_t b = c / K, k = c - b * K;
+    p0 = b * w + k * C;
+    lenfull = (int)min(C, w - k * C);
+    len = (int)min((int64_t)lenfull, n - p0);
+  };
+  {
+    int64_t p0;
+    int lf, ln;
+    geom(cw, p0, lf, ln);
+    crun_raw<T>(s, p0, w, ln, lf, cw >= c0 && p0 >= w, own, beh);
+  }
+  for (int64_t c = cw; c < c1; ++c) {
+    int64_t p0;
+    int lenfull, len;
+    geom(c, p0, lenfull, len);
+    const int64_t b = c / K, k = c - b * K;
+    const bool work = c >= c0;
+    const bool behind = work && b >= 1;
+    if (c + 1 < c1) {
+      int64_t q0;
+      int lf, ln;
+      geom(c + 1, q0, lf, ln);
+      crun_raw<T>(s, q0, w, ln, lf, c + 1 >= c0 && q0 >= w, nown, nbeh);
+    }
+    T ax[V], an[V], bx[V], bn[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int r = r0 + i;
+      const bool vo = r < len;
+      ax[i] = vo ? own[i] : Lim<T>::lo();
+      an[i] = vo ? own[i] : Lim<T>::hi();
+      const bool vb = behind && (r + 1 < lenfull);
+      bx[i] = vb ? beh[i] : Lim<T>::lo();
+      bn[i] = vb ? beh[i] : Lim<T>::hi();
+    }
+    if (work && s.carry != nullptr) {
+      const int64_t cs = n - min(n, w - 1);
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (r0 + i < len && p0 + r0 + i >= cs) gstore(s.carry + (p0 + r0 + i - cs), own[i]);
+    }
+#pragma unroll
+    for (int i = 1; i < V; ++i) {
+      ax[i] = vmax(ax[i - 1], ax[i]);
+      an[i] = vmin(an[i - 1], an[i]);
+    }
+#pragma unroll
+    for (int i = V - 2; i >= 0; --i) {
+      bx[i] = vmax(bx[i + 1], bx[i]);
+      bn[i] = vmin(bn[i + 1], bn[i]);
+    }
+    T epx = ax[V - 1], epn = an[V - 1], esx = bx[0], esn = bn[0], tx, tn;
+    wg_scan2<T>(epx, epn, esx, esn, tx, tn, sm);
+    if (tid == 0) {
+      sm.agx[c & (kCrRing - 1)] = tx;
+      sm.agn[c & (kCrRing - 1)] = tn;
+    }
+    const bool has_out = work && (p0 + len - 1) >= (w - 1);
+    if (has_out && tid < 64) {
+      // (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF: all in the ring
+      T prx = Lim<T>::lo(), prn = Lim<T>::hi(), sux = Lim<T>::lo(), sun = Lim<T>::hi();
+      for (int64_t u = c - (K - 1) + tid; u < c; u += 64) {
+        if (u >= 0) {
+          const T mx = sm.agx[u & (kCrRing - 1)], mn = sm.agn[u & (kCrRing - 1)];
+          if (u >= c - k) {
+            prx = vmax(prx, mx);
+            prn = vmin(prn, mn);
+          } else {
+            sux = vmax(sux, mx);
+            sun = vmin(sun, mn);
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        prx = vmax(prx, (T)__shfl_xor(prx, d, 64));
+        prn = vmin(prn, (T)__shfl_xor(prn, d, 64));
+        sux = vmax(sux, (T)__shfl_xor(sux, d, 64));
+        sun = vmin(sun, (T)__shfl_xor(sun, d, 64));
+      }
+      if (tid == 0) {
+        sm.dep[0] = prx;
+        sm.dep[1] = prn;
+        sm.dep[2] = sux;
+        sm.dep[3] = sun;
+      }
+    }
+    __syncthreads();
+    if (has_out) {
+      const T prx = vmax(sm.dep[0], epx), prn = vmin(sm.dep[1], epn);
+      const T sux = vmax(sm.dep[2], esx), sun = vmin(sm.dep[3], esn);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const int r = r0 + i;
+        if (r < len) {
+          sm.xs[lds_idx<T>(r)] = vmax(vmax(bx[i], sux), vmax(prx, ax[i]));
+          sm.hs[lds_idx<T>(r)] = vmin(vmin(bn[i], sun), vmin(prn, an[i]));
+        }
+      }
+      __syncthreads();
+      const int rs = (int)max((int64_t)0, (w - 1) - p0);
+      chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+      chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      own[i] = nown[i];
+      beh[i] = nbeh[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Persistent: XCD-aware static schedule over runs of `job.run` chunks.
+template <int MODE, class T>
+__global__ __launch_bounds__(kChunkThreads) void k_crun(Job<T> job) {
+  __shared__ CrunLds<T> sm;
+  const int64_t nruns = job_tiles<MODE>(job);
+  int64_t first, stride, end;
+  xcd_schedule(nruns, first, stride, end);
+  for (int64_t t = first; t < end; t += stride) {
+    int64_t local, gbase;
+    const Series<T> s = job_series<MODE>(job, t, local, gbase);
+    const int64_t nch = crun_chunks(s.n, s.w);
+    const int64_t c0 = local * job.run;
+    crun_body<T>(s, c0, min(nch, c0 + job.run), sm);
+  }
+}
+
 // ================================================================ batched
 // One workgroup: series descriptors, per-strategy tile counts and their
 // exclusive prefix sums (entry S holds the total).
@@ -822,14 +1012,15 @@ template <class K> static int occupancy_grid(K kernel, int threads) {
 }
 
 int grid_cap(int dtype, int strategy) {
-  static int cap[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  if (dtype < 0 || dtype > 3 || (strategy != kStratTile && strategy != kStratChunk)) return 0;
-  int& c = cap[strategy == kStratChunk][dtype];
+  static int cap[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratRun) return 0;
+  int& c = cap[strategy - 1][dtype];
   if (!c) {
-    dispatch(dtype, [&](auto* p) {
+    (void)dispatch(dtype, [&](auto* p) {
       using T = std::remove_pointer_t<decltype(p)>;
-      c = strategy == kStratTile ? occupancy_grid(k_tile<kJobDescs, T>, kTileThreads)
-                                 : occupancy_grid(k_chunk<kJobDescs, T>, kChunkThreads);
+      c = strategy == kStratTile    ? occupancy_grid(k_tile<kJobDescs, T>, kTileThreads)
+          : strategy == kStratChunk ? occupancy_grid(k_chunk<kJobDescs, T>, kChunkThreads)
+                                    : occupancy_grid(k_crun<kJobDescs, T>, kChunkThreads);
       return hipSuccess;
     });
   }
@@ -845,6 +1036,10 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
       if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T>), g, dim3(kTileThreads), 0, st, j);
       else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_tile<kJobDescs, T>), g, dim3(kTileThreads), 0, st, j);
       else hipLaunchKernelGGL((k_tile<kJobRows, T>), g, dim3(kTileThreads), 0, st, j);
+    } else if (strategy == kStratRun) {
+      if (a.mode == kJobOne) hipLaunchKernelGGL((k_crun<kJobOne, T>), g, dim3(kChunkThreads), 0, st, j);
+      else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_crun<kJobDescs, T>), g, dim3(kChunkThreads), 0, st, j);
+      else hipLaunchKernelGGL((k_crun<kJobRows, T>), g, dim3(kChunkThreads), 0, st, j);
     } else {
       if (a.mode == kJobOne) hipLaunchKernelGGL((k_chunk<kJobOne, T>), g, dim3(kChunkThreads), 0, st, j);
       else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_chunk<kJobDescs, T>), g, dim3(kChunkThreads), 0, st, j);

@@ -22,6 +22,20 @@ constexpr int kChunkThreads = 256;
 constexpr int kChunkV = 16;
 constexpr int kChunkMax = kChunkThreads * kChunkV;          // 4096
 
+// Chunk runs: window-aligned chunks of at most kCrMax inputs, aggregates in
+// an LDS ring of kCrRing chunks (so K = ceil(w / kCrMax) <= kCrRing).
+constexpr int kCrV = 8;
+constexpr int kCrMax = kChunkThreads * kCrV;                // 2048
+constexpr int kCrRing = 1024;
+
+__host__ __device__ inline int64_t crun_chunks(int64_t n, int64_t w) {
+  if (n < w || n <= 0) return 0;
+  int64_t K = (w + kCrMax - 1) / kCrMax;
+  int64_t C = (w + K - 1) / K;
+  int64_t last = n - 1;
+  return (last / w) * K + (last % w) / C + 1;
+}
+
 // Batched strategy selection happens on the device with the same rule as the
 // host planner's default: tile for w <= kTileMaxW, chunk otherwise.
 
@@ -75,7 +89,7 @@ struct JobArgs {
   Ctl* ctl = nullptr;
 };
 
-enum Strategy : int { kStratTile = 1, kStratChunk = 2 };
+enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3 };
 
 // Occupancy-derived persistent grid sizes (computed once per device).
 int grid_cap(int dtype, int strategy);

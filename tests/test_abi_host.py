@@ -60,6 +60,8 @@ def test_argument_errors_without_gpu(lib):
     assert lib.maxmin_filter_2d(0, None, 5, 5, 4, 2, 2, None, None, 4, None) == binding.MAXMIN_EINVAL  # ld < cols
     assert lib.maxmin_filter_2d(0, None, 5, 5, 5, 6, 2, None, None, 4, None) == binding.MAXMIN_OK  # no output
     assert lib.maxmin_set_strategy(9) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_set_strategy(3) == binding.MAXMIN_OK
+    assert lib.maxmin_set_strategy(0) == binding.MAXMIN_OK
     h = ctypes.c_void_p()
     assert lib.maxmin_stream_create(0, 0, ctypes.byref(h)) == binding.MAXMIN_EINVAL
     assert lib.maxmin_stream_push(None, None, 4, None, None, None, None) == binding.MAXMIN_EINVAL
@@ -83,11 +85,11 @@ def test_planner(lib):
     binding.maxmin_set_strategy(binding.STRATEGY_AUTO)
     assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_TILE
     assert binding.maxmin_plan(np.float32, 1 << 20, 1024) == binding.STRATEGY_TILE
-    assert binding.maxmin_plan(np.float32, 1 << 20, 1025) == binding.STRATEGY_CHUNK
+    assert binding.maxmin_plan(np.float32, 1 << 20, 1025) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)
     binding.maxmin_set_strategy(binding.STRATEGY_CHUNK)
     assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_CHUNK
     binding.maxmin_set_strategy(binding.STRATEGY_TILE)
-    assert binding.maxmin_plan(np.float32, 1 << 20, 5000) == binding.STRATEGY_CHUNK  # tile cannot
+    assert binding.maxmin_plan(np.float32, 1 << 20, 5000) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)  # tile cannot
     binding.maxmin_set_strategy(binding.STRATEGY_AUTO)
 
 

@@ -63,11 +63,11 @@ def test_plain_all_windows(dt):
             check(a, w, "n=%d w=%d %s" % (n, w, kind))
 
 
-@pytest.mark.parametrize("strategy", [mm.STRATEGY_TILE, mm.STRATEGY_CHUNK], ids=["tile", "chunk"])
+@pytest.mark.parametrize("strategy", [mm.STRATEGY_TILE, mm.STRATEGY_CHUNK, mm.STRATEGY_RUN], ids=["tile", "chunk", "run"])
 def test_forced_strategies_agree(strategy):
     rng = synth.rng_for("tests", 101)
     for dt in DTS:
-        for w in [1, 2, 5, 33, 100, 512, 700, 1024] + ([1025, 3000, 4097, 9000] if strategy == mm.STRATEGY_CHUNK else []):
+        for w in [1, 2, 5, 33, 100, 512, 700, 1024] + ([1025, 3000, 4097, 9000] if strategy != mm.STRATEGY_TILE else []):
             n = int(rng.integers(w, 3 * 2048 + w))
             a = gen(n, dt, rng, "walk" if w % 2 else "ties")
             note("forced=%d dt=%s n=%d w=%d" % (strategy, np.dtype(dt).name, n, w))
@@ -93,12 +93,13 @@ def test_misaligned_pointers():
                 check(a, w, "offset %d w=%d" % (off, w), offset=off)
 
 
-def test_large_windows():
+@pytest.mark.parametrize("strategy", [mm.STRATEGY_AUTO, mm.STRATEGY_CHUNK, mm.STRATEGY_RUN], ids=["auto", "chunk", "run"])
+def test_large_windows(strategy):
     rng = synth.rng_for("tests", 104)
     a = gen(300000, np.float32, rng, "walk")
-    for w in (4096, 65536, 100000, 299999, 300000):
-        note("large-w n=300000 w=%d" % w)
-        check(a, w, "w=%d" % w)
+    for w in (2048, 4096, 4100, 65536, 100000, 299999, 300000):
+        note("large-w n=300000 w=%d strategy=%d" % (w, strategy))
+        check(a, w, "w=%d" % w, strategy=strategy)
 
 
 def test_repeatable_bits():
