@@ -30,6 +30,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 WINDOWS = (16, 256, 4096, 65536)
+SERVING_RATES = (1000, 4000, 16000)
+SERVING_SECONDS = 6.0
 
 
 def alg_bytes(n, w, s):
@@ -206,6 +208,20 @@ def run_extras(torch, mm, synth, dev, stream):
         del o1, o2
     out["image"] = {"workload": "8192x8192 float32 Gaussian field + noise, rows then columns", "per_window": res}
     print("[bench] image done", file=sys.stderr, flush=True)
+    del xi
+
+    # serving: Poisson filter requests + 1000 persistent streams, 64 GB budget
+    from paper_cs_0610046_amd.serving import serving_run
+    srv = []
+    for rate in SERVING_RATES:
+        r = serving_run(rate, SERVING_SECONDS, n_streams=1000, stream_rate=10.0)
+        srv.append(r)
+        print("[bench] serving rate=%d p50=%s p99=%s ms" % (rate, r["p50_ms"], r["p99_ms"]), file=sys.stderr,
+              flush=True)
+    out["serving"] = {"workload": "Poisson filter requests (f32/f64/i32, n log-uniform [256, 4Mi], w uniform "
+                                  "[2, 8192]) + 1000 float32 streams x 10 chunks/s of 4096 at w=512; 64 GB HBM "
+                                  "budget, 4 lanes; latency = submit to completion incl. PCIe copies",
+                      "per_rate": srv}
     return out
 
 

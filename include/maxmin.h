@@ -138,6 +138,57 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
                      int64_t w_rows, int64_t w_cols, void* d_max, void* d_min, int64_t ld_out,
                      void* stream);
 
+/*
+ * Serving engine -- many callers submit filter requests and stream chunks
+ * (host buffers); the engine admits them against an HBM budget, batches the
+ * requests that have arrived into single launches (one per dtype and
+ * strategy) on one of `n_lanes` HIP streams, overlaps batches on the device,
+ * and reports each request's latency (submit to completion).  Stream carries
+ * (the last w-1 samples, Section 1's zero-latency streaming) stay resident on
+ * the device inside the budget.
+ *
+ * Buffers: h_in (n or m elements) and h_max/h_min (max(0, n-w+1) elements
+ * for a filter, m for a push) are HOST pointers owned by the caller and must
+ * stay valid until the request is returned by maxmin_engine_poll.  Use
+ * pinned memory (hipHostMalloc, torch pin_memory): pageable buffers make the
+ * engine's copies synchronous.  Requests with no complete window finish at
+ * once.  A request larger than the whole budget finishes with ENOMEM.
+ *
+ * maxmin_engine_create: budget >= 1 MiB (allocated up front), 1..16 lanes,
+ *   max_batch >= 1 requests per lane batch.  Errors: EINVAL, ENOMEM, EDEVICE.
+ * maxmin_engine_open_stream / close_stream: a stream of `dtype` with window w
+ *   (close waits for its queued pushes).
+ * maxmin_engine_submit_filter / submit_push: enqueue (thread-safe); *req_id
+ *   receives the request id.  Pushes of one stream complete in order.
+ * maxmin_engine_poll: up to `cap` finished requests since the last poll:
+ *   ids, n_out (windows written), latency in seconds, status; *got = count.
+ * maxmin_engine_drain: wait until every submitted request has finished.
+ * maxmin_engine_stats: out8 = {submitted, finished, batches, rejected,
+ *   samples processed, budget bytes in use, peak bytes in use, pending}.
+ * maxmin_engine_replay: open-loop load generator: submit request i at
+ *   at_s[i] seconds after the call (kind 0 filter with dtype/n/w, kind 1
+ *   push of n samples on stream sid[i]); req_ids and the submission lag
+ *   (seconds late) per request are optional outputs.
+ * maxmin_engine_destroy: drain, stop the engine threads, free everything.
+ */
+typedef struct maxmin_engine maxmin_engine_t;
+int maxmin_engine_create(int64_t hbm_budget_bytes, int n_lanes, int64_t max_batch, maxmin_engine_t** out);
+int maxmin_engine_open_stream(maxmin_engine_t* eng, int dtype, int64_t w, int64_t* stream_id);
+int maxmin_engine_close_stream(maxmin_engine_t* eng, int64_t stream_id);
+int maxmin_engine_submit_filter(maxmin_engine_t* eng, int dtype, const void* h_in, int64_t n, int64_t w,
+                                void* h_max, void* h_min, int64_t* req_id);
+int maxmin_engine_submit_push(maxmin_engine_t* eng, int64_t stream_id, const void* h_chunk, int64_t m,
+                              void* h_max, void* h_min, int64_t* req_id);
+int maxmin_engine_poll(maxmin_engine_t* eng, int64_t* ids, int64_t* n_out, double* latency_s, int* status,
+                       int64_t cap, int64_t* got);
+int maxmin_engine_drain(maxmin_engine_t* eng);
+int maxmin_engine_stats(maxmin_engine_t* eng, int64_t* out8);
+int maxmin_engine_replay(maxmin_engine_t* eng, int64_t count, const double* at_s, const int* kind,
+                         const int* dtype, const int64_t* n, const int64_t* w, const int64_t* sid,
+                         const void* const* h_in, void* const* h_max, void* const* h_min,
+                         int64_t* req_ids, double* lag_s);
+int maxmin_engine_destroy(maxmin_engine_t* eng);
+
 /* Force a strategy for subsequent 1-D calls from this process (AUTO restores
  * the planner).  Used by tests to check that every strategy gives the same
  * bits.  Errors: EINVAL on an unknown value. */

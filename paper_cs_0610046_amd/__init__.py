@@ -8,7 +8,7 @@ the binding loads the library on first use and raises if it is missing.
 """
 __all__ = ["maxmin_filter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
            "MaxMinStream", "maxmin_filter_2d", "maxmin_set_strategy", "maxmin_plan", "maxmin_check_stream",
-           "maxmin_last_error", "maxmin_version", "MaxMinError"]
+           "maxmin_last_error", "maxmin_version", "MaxMinError", "MaxMinEngine"]
 
 
 def __getattr__(name):

@@ -52,6 +52,23 @@ def lib():
         L.maxmin_set_strategy.argtypes = [ci]
         L.maxmin_plan.argtypes = [ci, i64, i64]
         L.maxmin_check_stream.argtypes = [vp]
+        vpp = ctypes.POINTER(vp)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.maxmin_engine_create.argtypes = [i64, ci, i64, vpp]
+        L.maxmin_engine_open_stream.argtypes = [vp, ci, i64, i64p]
+        L.maxmin_engine_close_stream.argtypes = [vp, i64]
+        L.maxmin_engine_submit_filter.argtypes = [vp, ci, vp, i64, i64, vp, vp, i64p]
+        L.maxmin_engine_submit_push.argtypes = [vp, i64, vp, i64, vp, vp, i64p]
+        L.maxmin_engine_poll.argtypes = [vp, i64p, i64p, dp, ip, i64, i64p]
+        L.maxmin_engine_drain.argtypes = [vp]
+        L.maxmin_engine_stats.argtypes = [vp, i64p]
+        L.maxmin_engine_replay.argtypes = [vp, i64, dp, ip, ip, i64p, i64p, i64p, vpp, vpp, vpp, i64p, dp]
+        L.maxmin_engine_destroy.argtypes = [vp]
+        for f in ("maxmin_engine_create", "maxmin_engine_open_stream", "maxmin_engine_close_stream",
+                  "maxmin_engine_submit_filter", "maxmin_engine_submit_push", "maxmin_engine_poll",
+                  "maxmin_engine_drain", "maxmin_engine_stats", "maxmin_engine_replay", "maxmin_engine_destroy"):
+            getattr(L, f).restype = ci
         L.maxmin_last_error.restype = ctypes.c_char_p
         L.maxmin_version.restype = ctypes.c_char_p
         for f in ("maxmin_filter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
@@ -231,3 +248,96 @@ def maxmin_last_error():
 
 def maxmin_version():
     return lib().maxmin_version().decode()
+
+
+def _hptr(a):
+    """Host address of a numpy array or a CPU torch tensor."""
+    if a is None:
+        return ctypes.c_void_p(0)
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class MaxMinEngine:
+    """maxmin_engine_*: serving loop with HBM admission and continuous
+    batching.  Buffers are host arrays (numpy, or pinned CPU torch tensors);
+    they must stay alive until their request is polled."""
+
+    def __init__(self, budget_bytes=64 << 30, lanes=4, max_batch=256):
+        h = ctypes.c_void_p()
+        _check(lib().maxmin_engine_create(int(budget_bytes), int(lanes), int(max_batch), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def open_stream(self, dtype, w):
+        sid = ctypes.c_int64()
+        _check(lib().maxmin_engine_open_stream(self._h, dtype_code(dtype), int(w), ctypes.byref(sid)))
+        return sid.value
+
+    def close_stream(self, sid):
+        _check(lib().maxmin_engine_close_stream(self._h, int(sid)))
+
+    def submit_filter(self, h_in, w, h_max, h_min, dtype=None):
+        rid = ctypes.c_int64()
+        dt = dtype_code(dtype if dtype is not None else h_in.dtype)
+        n = h_in.numel() if hasattr(h_in, "numel") else h_in.size
+        _check(lib().maxmin_engine_submit_filter(self._h, dt, _hptr(h_in), n, int(w), _hptr(h_max), _hptr(h_min),
+                                                 ctypes.byref(rid)))
+        self._keep[rid.value] = (h_in, h_max, h_min)
+        return rid.value
+
+    def submit_push(self, sid, h_chunk, h_max, h_min):
+        rid = ctypes.c_int64()
+        m = h_chunk.numel() if hasattr(h_chunk, "numel") else h_chunk.size
+        _check(lib().maxmin_engine_submit_push(self._h, int(sid), _hptr(h_chunk), m, _hptr(h_max), _hptr(h_min),
+                                               ctypes.byref(rid)))
+        self._keep[rid.value] = (h_chunk, h_max, h_min)
+        return rid.value
+
+    def poll(self, cap=65536):
+        """Finished requests: list of (id, n_out, latency_s, status)."""
+        ids = (ctypes.c_int64 * cap)()
+        no = (ctypes.c_int64 * cap)()
+        lat = (ctypes.c_double * cap)()
+        st = (ctypes.c_int * cap)()
+        got = ctypes.c_int64()
+        _check(lib().maxmin_engine_poll(self._h, ids, no, lat, st, cap, ctypes.byref(got)))
+        out = [(ids[i], no[i], lat[i], st[i]) for i in range(got.value)]
+        for r in out:
+            self._keep.pop(r[0], None)
+        return out
+
+    def drain(self):
+        _check(lib().maxmin_engine_drain(self._h))
+
+    def stats(self):
+        a = (ctypes.c_int64 * 8)()
+        _check(lib().maxmin_engine_stats(self._h, a))
+        keys = ("submitted", "finished", "batches", "rejected", "samples", "bytes_in_use", "peak_bytes", "pending")
+        return dict(zip(keys, list(a)))
+
+    def replay(self, at_s, kind, dtype, n, w, sid, h_in, h_max, h_min):
+        """Open-loop submission from a C++ thread (blocks until the last
+        request is submitted).  Returns (request ids, submission lag)."""
+        cnt = len(at_s)
+        A = lambda t, v: (t * cnt)(*v)  # noqa: E731
+        ids = (ctypes.c_int64 * cnt)()
+        lag = (ctypes.c_double * cnt)()
+        _check(lib().maxmin_engine_replay(
+            self._h, cnt, A(ctypes.c_double, at_s), A(ctypes.c_int, kind), A(ctypes.c_int, dtype),
+            A(ctypes.c_int64, n), A(ctypes.c_int64, w), A(ctypes.c_int64, sid),
+            A(ctypes.c_void_p, h_in), A(ctypes.c_void_p, h_max), A(ctypes.c_void_p, h_min), ids, lag))
+        return list(ids), list(lag)
+
+    def close(self):
+        if self._h:
+            _check(lib().maxmin_engine_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libmaxmin.so"
 LIB_PATH = os.path.join(OUT_DIR, LIB_NAME)
 
-SOURCES = ["mm_kernels_1d.hip", "mm_kernels_2d.hip", "mm_abi.cpp"]
+SOURCES = ["mm_kernels_1d.hip", "mm_kernels_2d.hip", "mm_abi.cpp", "mm_engine.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -264,6 +264,22 @@ bool g_graphs_enabled() {
 
 }  // namespace
 
+namespace mm {
+// Look-back state of `stream` (control words and a ring of at least
+// min(ntiles, 2^20) records), for launches made outside this file.
+int stream_lookback_state(hipStream_t stream, int64_t ntiles, uint64_t** ring, uint32_t* lg, Ctl** ctl) {
+  Workspace* ws = nullptr;
+  int r = get_ws(stream, &ws);
+  if (r) return r;
+  if ((r = ensure_ring(ws, ntiles))) return r;
+  *ring = ws->ring;
+  *lg = ws->ring_lg;
+  *ctl = ws->ctl;
+  return MAXMIN_OK;
+}
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace mm
+
 struct maxmin_stream {
   int dt;
   int64_t w;

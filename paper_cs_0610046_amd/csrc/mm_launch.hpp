@@ -108,6 +108,11 @@ hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st);
 
 size_t series_bytes();
 
+// Per-stream look-back state owned by the ABI layer (see mm_abi.cpp).
+int stream_lookback_state(hipStream_t stream, int64_t ntiles, uint64_t** ring, uint32_t* lg, Ctl** ctl);
+// Record a thread-local error message for maxmin_last_error; returns code.
+int set_error(int code, const char* msg);
+
 // 2-D column pass over the row-filtered images (rows x oc, leading
 // dimension ld_t): max-filter tmax's columns and min-filter tmin's.
 // Windows above cols_max_window(dtype) keep their per-block suffixes in a
