@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--n-log2", type=int, default=28)
     ap.add_argument("--extras", type=int, default=1, help="also run plain / batched / image workloads")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -68,6 +70,12 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = 1 << args.n_log2
     t0 = time.time()
     a = synth.random_walk(n, np.float32, synth.rng_for("large", 0))

@@ -56,6 +56,7 @@ size_t dsize(int dt) {
 bool aligned(const void* p, size_t s) { return ((uintptr_t)p % s) == 0; }
 
 std::atomic<int> g_force{0};
+constexpr int kDefaultChunkRanges = 16;
 
 int env_strategy() {
   static int v = -1;
@@ -159,7 +160,8 @@ int get_ws(hipStream_t s, Workspace** out) {
     delete ws;
     return fail(MAXMIN_ENOMEM, "hipMalloc(control words): %s", hipGetErrorString(e));
   }
-  mm::Ctl init = {0u, 0u, 1u, 0u};
+  mm::Ctl init{};
+  init.epoch = 1u;
   e = hipMemcpy(ws->ctl, &init, sizeof init, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(ws->ctl);
@@ -221,6 +223,18 @@ int ensure_tmp(Workspace* ws, size_t bytes) {
   return MAXMIN_OK;
 }
 
+// Ticket ranges for a single-series chunk launch (0, 1, 8, 16 or 32); the
+// environment variable MAXMIN_CHUNK_RANGES overrides the default.
+int chunk_ranges() {
+  int v = kDefaultChunkRanges;
+  const char* e = getenv("MAXMIN_CHUNK_RANGES");
+  if (e) {
+    const int x = atoi(e);
+    if (x == 0 || x == 1 || x == 8 || x == 16 || x == 32) v = x;
+  }
+  return v;
+}
+
 // Run one 1-D series (plain call or stream push) with the planned strategy.
 int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
   const int strat = plan_strategy(dt, a.n, a.w);
@@ -246,6 +260,7 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     a.ring = ws->ring;
     a.ring_lg = ws->ring_lg;
     a.ctl = ws->ctl;
+    a.ranges = chunk_ranges();
     const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratChunk));
     e = mm::launch_1d(dt, mm::kStratChunk, a, grid, st);
   }

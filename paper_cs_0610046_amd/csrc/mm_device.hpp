@@ -177,11 +177,14 @@ template <class T> __device__ __forceinline__ T from_bits(uint64_t b) {
 }
 
 // Per-launch control words in device memory (one set per HIP stream).
+constexpr int kMaxRanges = 32;
 struct Ctl {
   uint32_t ticket;  // next chunk tile to hand out (in-order tickets)
   uint32_t done;    // workgroups that have left the persistent loop
   uint32_t epoch;   // tags this launch's published aggregates
   uint32_t err;     // non-zero: a look-back wait gave up (never expected)
+  uint32_t pad[28];
+  uint32_t tick[kMaxRanges][32];  // per-range tickets, one 128-byte line each
 };
 
 // Look-back records of the chunk strategy: 2^lg records of 4 words each.
@@ -207,6 +210,7 @@ template <class T> struct Job {
   int64_t ld_out;
   int64_t tpr;            // rows: tiles per row
   int64_t run;            // tile strategy: windows per run (a multiple of the sub-tile)
+  int ranges;             // chunk strategy, single series: ticket ranges (0: one counter)
   FlagRing ring;          // chunk strategy only
   Ctl* ctl;
 };

@@ -526,9 +526,10 @@ __device__ __forceinline__ void chunk_store(T* out, const T* buf, int rs, int le
   for (int r = a0 + nv * EV + tid; r < len; r += NT) gstore(out + r, buf[lds_idx<T>(r)]);
 }
 
+// counter: where the next ticket comes from.
 template <class T>
 __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const FlagRing& ring, uint32_t ep,
-                           ChunkLds<T>& sm, Ctl* ctl, uint32_t& next) {
+                           ChunkLds<T>& sm, Ctl* ctl, uint32_t* counter, uint32_t& next) {
   constexpr int V = kChunkV;
   const int tid = threadIdx.x;
   const int64_t w = s.w, n = s.n;
@@ -625,7 +626,7 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   // Take the next ticket only now that this chunk waits on nothing: a ticket
   // taken earlier would sit unpublished behind this chunk's look-back and
   // stall the chunks that depend on it.  Its latency hides behind the stores.
-  if (tid == 0) next = add_agent32(&ctl->ticket, 1u);
+  if (tid == 0) next = add_agent32(counter, 1u);
   __syncthreads();
   if (has_out) {
     const T prx = vmax(sm.dep[0], epx), prn = vmin(sm.dep[1], epn);
@@ -654,23 +655,37 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   Ctl* ctl = job.ctl;
   const uint32_t ep = ld_agent32(&ctl->epoch);
   const int64_t ntiles = job_tiles<MODE>(job);
+  // A single series with one chunk per window (K = 1: no look-back) may
+  // split into R contiguous ranges of chunks, each with its own in-order
+  // tickets and served by the workgroups with blockIdx % R equal to its
+  // number.  Workgroup ids go round robin over the 8 XCDs, so with R a
+  // multiple of 8 a range stays on one XCD, and the chunk w back that each
+  // chunk re-reads was loaded there a moment earlier and is still in that
+  // XCD's L2.  The placement matters for speed only.  (With K > 1 the
+  // look-back chains ran slower split than whole on MI355X.)
+  const int R = MODE == kJobOne ? job.ranges : 0;
+  const bool split = R > 1 && ntiles >= 32 * (int64_t)R && (int)gridDim.x >= 8 * R && job.one.w <= kChunkMax;
+  const int cls = split ? (int)(blockIdx.x % R) : 0;
+  const int64_t rlo = split ? ntiles * cls / R : 0, rhi = split ? ntiles * (cls + 1) / R : ntiles;
+  uint32_t* counter = split ? &ctl->tick[cls][0] : &ctl->ticket;
   // thread 0 takes each next ticket while the current chunk stores its outputs
   uint32_t next = 0;
-  if (threadIdx.x == 0) next = add_agent32(&ctl->ticket, 1u);
+  if (threadIdx.x == 0) next = add_agent32(counter, 1u);
   for (;;) {
     if (threadIdx.x == 0) sm.ticket = next;
     __syncthreads();
-    const int64_t t = sm.ticket;
-    if (t >= ntiles) break;
+    const int64_t t = rlo + (int64_t)sm.ticket;
+    if (t >= rhi) break;
     int64_t local, gbase;
     const Series<T> s = job_series<MODE>(job, t, local, gbase);
-    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl, next);
+    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl, counter, next);
   }
   // the last workgroup out re-arms the control words for the next launch
   if (threadIdx.x == 0) {
     const uint32_t d = add_agent32(&ctl->done, 1u);
     if (d == gridDim.x - 1) {
       st_agent32(&ctl->ticket, 0u);
+      for (int i = 0; i < R && i < kMaxRanges; ++i) st_agent32(&ctl->tick[i][0], 0u);
       st_agent32(&ctl->done, 0u);
       uint32_t e = ep + 1u;
       if (e == 0u) e = 1u;
@@ -987,6 +1002,7 @@ template <class T> static Job<T> make_job(const JobArgs& a) {
   j.ld_out = a.ld_out;
   j.tpr = a.tpr;
   j.run = a.run;
+  j.ranges = a.ranges;
   j.ring.f = a.ring;
   j.ring.lg = a.ring_lg;
   j.ctl = a.ctl;

@@ -83,6 +83,7 @@ struct JobArgs {
   int64_t ld_out = 0;
   int64_t tpr = 0;
   int64_t run = 0;  // tile strategy: windows per run
+  int ranges = 0;   // chunk strategy, single series: ticket ranges (0 or 1: one counter)
   // chunk strategy look-back state
   uint64_t* ring = nullptr;
   uint32_t ring_lg = 0;

@@ -102,6 +102,20 @@ def test_large_windows(strategy):
         check(a, w, "w=%d" % w, strategy=strategy)
 
 
+@pytest.mark.parametrize("ranges", ["0", "8", "16", "32"])
+def test_chunk_ticket_ranges(ranges, monkeypatch):
+    """One-chunk windows (1024 < w <= 4096) split the chunks of a series
+    into per-XCD ticket ranges; every range count gives the oracle's bits,
+    with chunk counts that do not divide evenly into the ranges."""
+    monkeypatch.setenv("MAXMIN_CHUNK_RANGES", ranges)
+    rng = synth.rng_for("tests", 106)
+    for dt in (np.float32, np.float64):
+        for w, n in ((1025, 1100003), (1500, 1500 * 700 + 311), (4096, 4096 * 1031 + 4095)):
+            a = gen(n, dt, rng, "walk")
+            note("ranges=%s dt=%s n=%d w=%d" % (ranges, np.dtype(dt).name, n, w))
+            check(a, w, "ranges=%s n=%d w=%d" % (ranges, n, w))
+
+
 def test_repeatable_bits():
     import torch
     rng = synth.rng_for("tests", 105)
