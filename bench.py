@@ -9,11 +9,13 @@ the K timed steps (Gelem/s), inputs already resident in HBM.
 Also reported on the same JSON line (not part of ``value``):
 * ``per_window``   -- each window's launch time, Gelem/s and % of 8 TB/s
   (algorithmic bytes: n*s read + 2*(n-w+1)*s written),
+* ``roofline``     -- the dominant kernel (most time per step) against HBM
+  peak, with its measured HBM traffic per launch when the committed counter
+  summary matches the current kernel sources,
 * ``plain``        -- n = 2**20 float32, w = 64 (latency-bound),
 * ``batched``      -- 10,000 float32 random walks, lengths log-uniform in
   [1e3, 1e6], windows uniform in [2, 1024], one batched call (graph replay),
 * ``image``        -- 8192 x 8192 float32, w x w windows, rows then columns,
-* ``roofline``     -- the dominant kernel against HBM peak,
 * ``cpu_baseline`` -- the CPU oracle (single thread) on a bounded sample.
 """
 import argparse
@@ -36,6 +38,47 @@ SERVING_SECONDS = 6.0
 
 def alg_bytes(n, w, s):
     return n * s + 2 * max(0, n - w + 1) * s
+
+
+def kernel_name(strategy):
+    return "mm::k_%s<0, float>" % strategy
+
+
+# Sources whose change invalidates counter-derived traffic figures.
+KERNEL_SOURCES = ("paper_cs_0610046_amd/csrc/mm_kernels_1d.hip", "paper_cs_0610046_amd/csrc/mm_device.hpp",
+                  "paper_cs_0610046_amd/csrc/mm_launch.hpp", "paper_cs_0610046_amd/csrc/mm_abi.cpp")
+TRAFFIC_FILE = "profiles/hbm_traffic_f32_walk_n2p28.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary,
+    or None when it is missing, for another size, or older than the kernel
+    sources (its recorded source hash differs)."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if n != 1 << 28 or not os.path.exists(path):
+        return None, "none"
+    vals, src = {}, None
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("source-hash:"):
+            src = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic-per-launch:"):
+            k, v = line.split(":", 1)[1].rsplit("=", 1)
+            vals[k.strip()] = float(v)
+    if src != kernel_source_hash():
+        return None, "stale (kernel sources changed since the counters were taken)"
+    if kernel not in vals:
+        return None, "none"
+    return vals[kernel], TRAFFIC_FILE
 
 
 def timed(fn, iters, stream):
@@ -118,13 +161,25 @@ def main():
         per_window[str(w)] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                               "alg_GBs": round(gb, 1), "pct_hbm": round(100 * gb / HBM_PEAK_GBS, 1),
                               "strategy": "tile" if mm.maxmin_plan(torch.float32, n, w) == 1 else "chunk"}
-    dom = max(WINDOWS, key=lambda w: np.mean(ev[w]))
-    dom_ms = float(np.mean(ev[dom]))
-    achieved = alg_bytes(n, dom, 4) / (dom_ms * 1e-3) / 1e9
+    # the dominant kernel: the one with the most time per step; its roofline
+    # point is its algorithmic bytes over its launches / their total time
+    kern = {}
+    for w in WINDOWS:
+        k = kernel_name(per_window[str(w)]["strategy"])
+        kern.setdefault(k, []).append(w)
+    dom = max(kern, key=lambda k: sum(np.mean(ev[w]) for w in kern[k]))
+    dom_ms = float(np.mean([t for w in kern[dom] for t in ev[w]]))
+    dom_bytes = float(np.mean([alg_bytes(n, w, 4) for w in kern[dom]]))
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic, tsrc = measured_traffic(dom, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_%s<float> (w=%d)" % (per_window[str(dom)]["strategy"], dom),
-                "alg_bytes_per_launch": alg_bytes(n, dom, 4), "avg_launch_ms": round(dom_ms, 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(round(traffic)),
+                "traffic_unit": "bytes per launch (HBM, calibrated FETCH_SIZE + WRITE_SIZE)",
+                "traffic_vs_alg": None if traffic is None else round(traffic / dom_bytes, 4),
+                "traffic_source": tsrc,
+                "kernel": dom, "windows": kern[dom], "alg_bytes_per_launch": int(dom_bytes),
+                "avg_launch_ms": round(dom_ms, 4)}
     print("[bench] headline %.1f Gelem/s, %.3f ms/step" % (value, ms_per_step), file=sys.stderr, flush=True)
     del outs
 
