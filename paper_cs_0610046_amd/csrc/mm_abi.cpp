@@ -242,6 +242,10 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
   if (strat == MAXMIN_STRATEGY_TILE) {
     const int cap = mm::grid_cap(dt, mm::kStratTile);
     a.run = mm::run_length(a.n - a.w + 1, cap);
+    if (const char* e = getenv("MAXMIN_TILE_RUN")) {
+      const int64_t r = atoll(e) / mm::kTileOut * mm::kTileOut;
+      if (r > 0 && r < a.run) a.run = r;
+    }
     a.ntiles = mm::run_count(a.n, a.w, a.run);
     const int grid = (int)std::min<int64_t>(a.ntiles, cap);
     e = mm::launch_1d(dt, mm::kStratTile, a, grid, st);

@@ -141,20 +141,144 @@ template <class T> struct TileLds {
   T pn[lds_len<T>(2 * kTileOut)];  // PRE (min) ring
 };
 
-// Load the 8 inputs at positions p .. p+7 (those >= lim read as 0, never used).
+// Series and outputs need not be 16-byte aligned (a packed batch puts
+// series at arbitrary element offsets).  A wavefront covers 64 * 8
+// consecutive positions, a multiple of 16 bytes, so all its lanes share one
+// misalignment D (in elements): lanes then load (store) the aligned 16-byte
+// vectors shifted by D and pass the D elements that cross a lane boundary to
+// the neighbouring lane with one shuffle each; the wavefront's edge lanes
+// load (store) those few elements singly.
+
+// v[i] = input p + i, from aligned vectors holding p - D .. p - D + 7
+template <class T, int D>
+__device__ __forceinline__ void load_shifted(const T* vb, int64_t p, T (&v)[kTileV]) {
+  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
+  T raw[V];
+#pragma unroll
+  for (int k = 0; k < V / EV; ++k) {
+    const u32x4 u = gload((const u32x4*)(vb + p - D + k * EV));
+    __builtin_memcpy(&raw[k * EV], &u, 16);
+  }
+  T nb[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) nb[j] = shdn(raw[j], 1, 64);
+#pragma unroll
+  for (int i = 0; i < V - D; ++i) v[i] = raw[i + D];
+  if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+    for (int i = V - D; i < V; ++i) v[i] = gload(vb + p + i);
+  } else {
+#pragma unroll
+    for (int i = V - D; i < V; ++i) v[i] = nb[i - (V - D)];
+  }
+}
+
+// store o[i] at out[i] (i < 8) with aligned vectors starting at out + D
+template <class T, int D>
+__device__ __forceinline__ void store_shifted(T* out, const T (&o)[kTileV]) {
+  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
+  const int lane = threadIdx.x & 63;
+  T nb[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) nb[j] = shdn(o[j], 1, 64);
+#pragma unroll
+  for (int k = 0; k < V / EV; ++k) {
+    if (D + (k + 1) * EV > V && lane == 63) {
+      // the vector would reach into the next wavefront's positions
+#pragma unroll
+      for (int i = D + k * EV; i < V; ++i) gstore(out + i, o[i]);
+    } else {
+      T e[EV];
+#pragma unroll
+      for (int x = 0; x < EV; ++x) {
+        const int i = D + k * EV + x;
+        e[x] = i < V ? o[i] : nb[i - V];
+      }
+      u32x4 u;
+      __builtin_memcpy(&u, e, 16);
+      gstore((u32x4*)(out + D + k * EV), u);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) gstore(out + i, o[i]);
+  }
+}
+
+// Load the 8 inputs at positions p .. p+7 (those >= lim read as 0, never
+// used).  vb: the segment base (element i at vb + i) or null; d: the
+// misalignment of vb + p in elements.
 template <class T>
-__device__ __forceinline__ void run_load(const Series<T>& s, const T* vbase, int64_t p, int64_t lim,
+__device__ __forceinline__ void run_load(const Series<T>& s, const T* vb, int d, int64_t p, int64_t lim,
                                          T (&v)[kTileV]) {
   constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
-  if (vbase != nullptr && p + V <= lim) {
+  const int64_t pw = p - (int64_t)(threadIdx.x & 63) * V;  // the wavefront's first position
+  if (vb != nullptr && pw + 64 * V <= lim) {
+    switch (d) {
+      case 0:
 #pragma unroll
-    for (int k = 0; k < V / EV; ++k) {
-      const u32x4 u = gload((const u32x4*)(vbase + p + k * EV));
-      __builtin_memcpy(&v[k * EV], &u, 16);
+        for (int k = 0; k < V / EV; ++k) {
+          const u32x4 u = gload((const u32x4*)(vb + p + k * EV));
+          __builtin_memcpy(&v[k * EV], &u, 16);
+        }
+        break;
+      case 1: load_shifted<T, 1>(vb, p, v); break;
+      case 2: if constexpr (EV > 2) load_shifted<T, 2>(vb, p, v); break;
+      case 3: if constexpr (EV > 3) load_shifted<T, 3>(vb, p, v); break;
+      case 4: if constexpr (EV > 4) load_shifted<T, 4>(vb, p, v); break;
+      case 5: if constexpr (EV > 5) load_shifted<T, 5>(vb, p, v); break;
+      case 6: if constexpr (EV > 6) load_shifted<T, 6>(vb, p, v); break;
+      default: if constexpr (EV > 7) load_shifted<T, 7>(vb, p, v); break;
     }
   } else {
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = (p + i < lim) ? src_at(s, p + i) : T(0);
+  }
+}
+
+// Store the 8 outputs of positions q .. q+7 (only those < R1).  ovec: the
+// max and min outputs share the misalignment d (elements) at position q.
+template <class T>
+__device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_t q, int64_t R1,
+                                          const T (&ox)[kTileV], const T (&on_)[kTileV]) {
+  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
+  const int64_t qw = q - (int64_t)(threadIdx.x & 63) * V;
+  if (ovec && qw + 64 * V <= R1) {
+    const int sh = (EV - d) & (EV - 1);  // elements before the first aligned vector
+    switch (sh) {
+      case 0:
+#pragma unroll
+        for (int k = 0; k < V / EV; ++k) {
+          u32x4 a, b;
+          __builtin_memcpy(&a, &ox[k * EV], 16);
+          __builtin_memcpy(&b, &on_[k * EV], 16);
+          gstore((u32x4*)(om + k * EV), a);
+          gstore((u32x4*)(on + k * EV), b);
+        }
+        break;
+#define MM_STORE_CASE(D)                \
+  case D:                               \
+    if constexpr (EV > D) {             \
+      store_shifted<T, D>(om, ox);      \
+      store_shifted<T, D>(on, on_);     \
+    }                                   \
+    break;
+      MM_STORE_CASE(1)
+      MM_STORE_CASE(2)
+      MM_STORE_CASE(3)
+      MM_STORE_CASE(4)
+      MM_STORE_CASE(5)
+      MM_STORE_CASE(6)
+      MM_STORE_CASE(7)
+#undef MM_STORE_CASE
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (q + i < R1) {
+        gstore(om + i, ox[i]);
+        gstore(on + i, on_[i]);
+      }
   }
 }
 
@@ -170,20 +294,23 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   const int64_t nout = s.n - s.w + 1;
   const int64_t lim = min(s.n, R1 + (int64_t)w - 1);  // inputs used: [R0, lim)
   const int nsub = (int)((R1 - 1 - R0) / TT) + 2;     // sub-tiles P_0 .. P_{nsub-1}
-  // 16-byte loads when [R0, lim) lies in one aligned source segment
+  // 16-byte loads when [R0, lim) lies in one source segment
+  constexpr int EV = 16 / (int)sizeof(T);
   const T* vbase = nullptr;
   if (lim <= s.na) vbase = s.a;
   else if (R0 >= s.na) vbase = s.b - s.na;
-  if (vbase != nullptr && ((((uintptr_t)(vbase + R0)) & 15) != 0)) vbase = nullptr;
-  const bool ovec = ((((uintptr_t)(s.omax + R0)) | ((uintptr_t)(s.omin + R0))) & 15) == 0;
+  const int din = vbase != nullptr ? (int)(((uintptr_t)(vbase + R0) / sizeof(T)) & (EV - 1)) : 0;
+  const int dmx = (int)(((uintptr_t)(s.omax + R0) / sizeof(T)) & (EV - 1));
+  const int dmn = (int)(((uintptr_t)(s.omin + R0) / sizeof(T)) & (EV - 1));
+  const bool ovec = dmx == dmn;
   const bool last_run = R1 == nout;
 
   T cur[V], nxt[V];
   T sx[V], sn[V];  // SUF of the previous sub-tile's positions
-  run_load<T>(s, vbase, R0 + tid * V, lim, cur);
+  run_load<T>(s, vbase, din, R0 + tid * V, lim, cur);
   for (int k = 0; k < nsub; ++k) {
     const int pr0 = k * TT + tid * V;  // position of cur[0], relative to R0
-    if (k + 1 < nsub) run_load<T>(s, vbase, R0 + pr0 + TT, lim, nxt);
+    if (k + 1 < nsub) run_load<T>(s, vbase, din, R0 + pr0 + TT, lim, nxt);
     if (s.carry != nullptr && last_run) {
       // the series' last w-1 inputs are the next push's carry
 #pragma unroll
@@ -278,26 +405,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         on[i] = rn;
       }
       const int64_t q0 = R0 + qr0;
-      T* om = s.omax + q0;
-      T* on_ = s.omin + q0;
-      if (ovec && q0 + V <= R1) {
-        constexpr int NV = V * (int)sizeof(T) / 16, EV = 16 / (int)sizeof(T);
-#pragma unroll
-        for (int k2 = 0; k2 < NV; ++k2) {
-          u32x4 a, b;
-          __builtin_memcpy(&a, &ox[k2 * EV], 16);
-          __builtin_memcpy(&b, &on[k2 * EV], 16);
-          gstore((u32x4*)(om + k2 * EV), a);
-          gstore((u32x4*)(on_ + k2 * EV), b);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < V; ++i)
-          if (q0 + i < R1) {
-            gstore(om + i, ox[i]);
-            gstore(on_ + i, on[i]);
-          }
-      }
+      run_store<T>(s.omax + q0, s.omin + q0, ovec, dmx, q0, R1, ox, on);
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {

@@ -93,6 +93,30 @@ def test_misaligned_pointers():
                 check(a, w, "offset %d w=%d" % (off, w), offset=off)
 
 
+def test_misaligned_outputs():
+    """Input, max and min pointers at independent element offsets (each
+    misalignment modulo 16 bytes, equal and unequal between the outputs),
+    over several wavefronts, runs and a ragged tail."""
+    import torch
+    rng = synth.rng_for("tests", 107)
+    for dt in DTS:
+        tdt = to_dev(np.zeros(1, dt)).dtype
+        for oi, ox, on in ((0, 1, 1), (1, 2, 2), (3, 1, 2), (5, 7, 7), (2, 0, 3), (7, 6, 0)):
+            for w in (3, 300, 1000):
+                n = 70001 + oi
+                a = gen(n, dt, rng, "walk")
+                buf = to_dev(np.concatenate([np.zeros(oi, dt), a]))
+                no = n - w + 1
+                bmx = torch.empty(no + 8, dtype=tdt, device="cuda")
+                bmn = torch.empty(no + 8, dtype=tdt, device="cuda")
+                note("misaligned-out dt=%s in=%d max=%d min=%d w=%d" % (np.dtype(dt).name, oi, ox, on, w))
+                mm.maxmin_filter(buf[oi:], w, bmx[ox:ox + no], bmn[on:on + no])
+                torch.cuda.synchronize()
+                omx, omn = oracle.wedge(a, w)
+                assert_bits_equal(to_host(bmx[ox:ox + no], dt), omx, "max offsets %d/%d/%d" % (oi, ox, on))
+                assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "min offsets %d/%d/%d" % (oi, ox, on))
+
+
 @pytest.mark.parametrize("strategy", [mm.STRATEGY_AUTO, mm.STRATEGY_CHUNK, mm.STRATEGY_RUN], ids=["auto", "chunk", "run"])
 def test_large_windows(strategy):
     rng = synth.rng_for("tests", 104)
