@@ -143,6 +143,11 @@ template <class T> __device__ __forceinline__ T gload(const T* p) {
 template <class T> __device__ __forceinline__ void gstore(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
+// Streaming store (nontemporal hint).  On MI355X it sped up the chunk
+// kernel's staged 16-byte output stores by ~3% and slowed the tile kernel's.
+template <class T> __device__ __forceinline__ void gstore_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)p);
+}
 
 template <class T> __device__ __forceinline__ T src_at(const Series<T>& s, int64_t i) {
   return i < s.na ? gload(s.a + i) : gload(s.b + (i - s.na));

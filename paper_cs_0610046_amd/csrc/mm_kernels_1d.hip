@@ -417,14 +417,13 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   }
 }
 
-// Persistent: XCD-aware static schedule over runs.
+// Persistent: static round-robin over runs (runs share no data beyond a
+// w-1 halo; on MI355X this beat the XCD-contiguous schedule by ~2%).
 template <int MODE, class T>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
   __shared__ TileLds<T> sm;
   const int64_t nruns = job_tiles<MODE>(job);
-  int64_t first, stride, end;
-  xcd_schedule(nruns, first, stride, end);
-  for (int64_t t = first; t < end; t += stride) {
+  for (int64_t t = blockIdx.x; t < nruns; t += gridDim.x) {
     int64_t local, gbase;
     const Series<T> s = job_series<MODE>(job, t, local, gbase);
     const int64_t nout = s.n - s.w + 1;
@@ -629,7 +628,7 @@ __device__ __forceinline__ void chunk_store(T* out, const T* buf, int rs, int le
     for (int k = 0; k < EV; ++k) e[k] = buf[lds_idx<T>(a0 + v * EV + k)];
     u32x4 u;
     __builtin_memcpy(&u, e, 16);
-    gstore((u32x4*)(out + a0 + v * EV), u);
+    gstore_nt((u32x4*)(out + a0 + v * EV), u);
   }
   for (int r = a0 + nv * EV + tid; r < len; r += NT) gstore(out + r, buf[lds_idx<T>(r)]);
 }
