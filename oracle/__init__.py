@@ -15,13 +15,17 @@ Comparisons per Element".
   -- the 2-D rectangle definition.
 * :func:`batched` / :func:`out_offsets` -- one filter per series of a packed
   buffer (independent series; the per-series call is the 1-D oracle).
+* :func:`argnaive` -- the leftmost location of each window's max and min,
+  from the definition; :func:`argdeque` -- the same in linear time (the
+  arg max/min filter the paper notes comes free with stored locations,
+  Section 5; ties: leftmost).
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 (brute force on tiny inputs, numpy/scipy library routines, closed forms,
 invariants, hand-built worked examples and the paper's comparison bounds).
 """
 from .oracle import (DTYPES, build, load, naive, wedge, Stream, filter2d,
-                     naive2d, batched, out_offsets, n_out)
+                     naive2d, batched, out_offsets, n_out, argnaive, argdeque)
 
 __all__ = ["DTYPES", "build", "load", "naive", "wedge", "Stream", "filter2d",
-           "naive2d", "batched", "out_offsets", "n_out"]
+           "naive2d", "batched", "out_offsets", "n_out", "argnaive", "argdeque"]

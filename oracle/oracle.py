@@ -62,6 +62,9 @@ def load():
         for f in (lib.oracle_filter2d, lib.oracle_naive2d):
             f.argtypes = [ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _i64]
             f.restype = ctypes.c_int
+        for f in (lib.oracle_argnaive, lib.oracle_argdeque):
+            f.argtypes = [ctypes.c_int, _vp, _i64, _i64, _vp, _vp]
+            f.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -115,6 +118,30 @@ def wedge(a, w, count=False):
     if count:
         return mx, mn, c.value, p.value
     return mx, mn
+
+
+def _arg(fn, a, w):
+    a = np.ascontiguousarray(a)
+    if int(w) < 1:
+        raise ValueError("w must be >= 1")
+    k = n_out(a.size, w)
+    imx = np.empty(k, np.int64)
+    imn = np.empty(k, np.int64)
+    if fn(_code(a), _ptr(a), a.size, int(w), _ptr(imx), _ptr(imn)) != 0:
+        raise ValueError("bad arguments")
+    return imx, imn
+
+
+def argnaive(a, w):
+    """Leftmost locations of each window's max and min, from the definition
+    (O(n*w))."""
+    return _arg(load().oracle_argnaive, a, w)
+
+
+def argdeque(a, w):
+    """The same locations in linear time (monotonic deques of locations that
+    keep equal values), pinned to :func:`argnaive`."""
+    return _arg(load().oracle_argdeque, a, w)
 
 
 class Stream:

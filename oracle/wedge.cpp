@@ -18,6 +18,15 @@
 //                  (Section 1, image-processing paragraph).
 //   * naive2d_*    the 2-D definition written out (max/min over every
 //                  w_rows x w_cols rectangle), to pin filter2d.
+//   * argnaive     the locations of the window maxima and minima, from the
+//                  definition: the leftmost location attaining the window's
+//                  max (min).  The paper notes that an implementation that
+//                  stores locations gives this arg max/min filter at no
+//                  extra cost (Section 5); it fixes no rule for ties.
+//   * argdeque     the same locations from a monotonic deque of locations
+//                  that drops only strictly dominated entries (so equal
+//                  values stay and the front is the leftmost), pinned to
+//                  argnaive; linear time, for large tests.
 //
 // Every value operation is a comparison followed by a selection, so all
 // results are exact for every dtype.  Indices are 64-bit (Section 5 advises
@@ -37,6 +46,10 @@
 //       (w = 1 is the identity).
 //   R6  Only comparisons between values are counted (Section 1 cost model);
 //       emptiness and index tests are not.
+//   R7  Locations: the paper's update sends an element equal to its
+//       predecessor to L and so does not always return the leftmost minimum
+//       among ties; the location outputs here follow one rule for both: the
+//       leftmost location of the window's max (min).
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -195,6 +208,42 @@ void naive2d(const T* a, int64_t rows, int64_t cols, int64_t ld, int64_t wr,
     }
 }
 
+// Locations (0-based, in the series) of the leftmost max and min of every
+// window, scanned directly.
+template <class T>
+void argnaive(const T* a, int64_t n, int64_t w, int64_t* amx, int64_t* amn) {
+  for (int64_t j = 0; j + w <= n; ++j) {
+    int64_t im = j, in = j;
+    for (int64_t i = j + 1; i < j + w; ++i) {
+      if (a[i] > a[im]) im = i;  // strict: an equal later value never wins
+      if (a[i] < a[in]) in = i;
+    }
+    amx[j] = im;
+    amn[j] = in;
+  }
+}
+
+// Same result in linear time: U holds locations with non-increasing values
+// (front = leftmost max of the window), L non-decreasing (front = leftmost
+// min).  A new value removes only the entries it strictly dominates.
+template <class T>
+void argdeque(const T* a, int64_t n, int64_t w, int64_t* amx, int64_t* amn) {
+  std::deque<int64_t> U, L;
+  for (int64_t i = 0; i < n; ++i) {
+    const T x = a[i];
+    while (!U.empty() && a[U.back()] < x) U.pop_back();
+    U.push_back(i);
+    while (!L.empty() && a[L.back()] > x) L.pop_back();
+    L.push_back(i);
+    if (U.front() <= i - w) U.pop_front();
+    if (L.front() <= i - w) L.pop_front();
+    if (i >= w - 1) {
+      amx[i - w + 1] = U.front();
+      amn[i - w + 1] = L.front();
+    }
+  }
+}
+
 // dtype codes shared with the Python wrapper: 0 f32, 1 f64, 2 i32, 3 u16.
 struct StreamBox {
   int dt;
@@ -286,6 +335,18 @@ int oracle_naive2d(int dt, const void* a, int64_t rows, int64_t cols, int64_t ld
                    int64_t wr, int64_t wc, void* mx, void* mn, int64_t ldo) {
   if (wr < 1 || wc < 1 || rows < 0 || cols < 0 || ld < cols) return -1;
   ORACLE_DISPATCH(dt, naive2d<T>((const T*)a, rows, cols, ld, wr, wc, (T*)mx, (T*)mn, ldo));
+  return 0;
+}
+
+int oracle_argnaive(int dt, const void* a, int64_t n, int64_t w, int64_t* amx, int64_t* amn) {
+  if (w < 1 || n < 0) return -1;
+  ORACLE_DISPATCH(dt, argnaive<T>((const T*)a, n, w, amx, amn));
+  return 0;
+}
+
+int oracle_argdeque(int dt, const void* a, int64_t n, int64_t w, int64_t* amx, int64_t* amn) {
+  if (w < 1 || n < 0) return -1;
+  ORACLE_DISPATCH(dt, argdeque<T>((const T*)a, n, w, amx, amn));
   return 0;
 }
 

@@ -29,9 +29,17 @@ MUTATIONS = [
     ("inner comparison not counted", "          if (COUNT) ++ncmp;\n          if (x > U.back().second)",
      "          if (x > U.back().second)"),
     ("emission one sample late", "if (t >= w) {  // R4", "if (t >= w + 1) {  // R4"),
-    ("naive window one short", "for (int64_t i = j + 1; i < j + w; ++i)", "for (int64_t i = j + 1; i < j + w - 1; ++i)"),
+    ("naive window one short", "for (int64_t i = j + 1; i < j + w; ++i) {\n      if (a[i] > M)",
+     "for (int64_t i = j + 1; i < j + w - 1; ++i) {\n      if (a[i] > M)"),
+    ("arg window one short", "for (int64_t i = j + 1; i < j + w; ++i) {\n      if (a[i] > a[im])",
+     "for (int64_t i = j + 1; i < j + w - 1; ++i) {\n      if (a[i] > a[im])"),
     ("2-D max taken from the min image", "col[(size_t)r] = rmax[(size_t)(r * oc + c)];",
      "col[(size_t)r] = rmin[(size_t)(r * oc + c)];"),
+    ("arg max tie resolved to the right", "if (a[i] > a[im]) im = i;", "if (a[i] >= a[im]) im = i;"),
+    ("arg min location off by one", "amn[j] = in;", "amn[j] = in + (in > j ? -1 : 0);"),
+    ("deque drops equal values", "while (!U.empty() && a[U.back()] < x) U.pop_back();",
+     "while (!U.empty() && a[U.back()] <= x) U.pop_back();"),
+    ("deque expires one sample late", "if (L.front() <= i - w) L.pop_front();", "if (L.front() < i - w) L.pop_front();"),
 ]
 
 
@@ -47,6 +55,8 @@ def _compile(src_text, d):
     lib.oracle_wedge.restype = i64
     lib.oracle_naive.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp]
     lib.oracle_filter2d.argtypes = [ctypes.c_int, vp, i64, i64, i64, i64, i64, vp, vp, i64]
+    lib.oracle_argnaive.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp]
+    lib.oracle_argdeque.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp]
     return lib
 
 
@@ -81,6 +91,24 @@ def _pins_pass(lib):
         for fn in ("wedge", "naive"):
             mx, mn, _, _ = call(fn, a, w)
             if not (np.array_equal(mx, v.max(1)) and np.array_equal(mn, v.min(1))):
+                return False
+    for fn in (lib.oracle_argnaive, lib.oracle_argdeque):
+        for ex in GOLD["arg"]:
+            a = np.array(ex["a"], np.float64)
+            k = a.size - ex["w"] + 1
+            imx, imn = np.zeros(k, np.int64), np.zeros(k, np.int64)
+            fn(1, a.ctypes.data, a.size, ex["w"], imx.ctypes.data, imn.ctypes.data)
+            if imx.tolist() != ex["argmax"] or imn.tolist() != ex["argmin"]:
+                return False
+        for it in range(100):
+            n = int(rng.integers(1, 60))
+            w = int(rng.integers(1, n + 1))
+            a = rng.integers(0, 4, n).astype(np.float64)
+            v = sliding_window_view(a, w)
+            j = np.arange(v.shape[0])
+            imx, imn = np.zeros(j.size, np.int64), np.zeros(j.size, np.int64)
+            fn(1, a.ctypes.data, a.size, w, imx.ctypes.data, imn.ctypes.data)
+            if not (np.array_equal(imx, v.argmax(1) + j) and np.array_equal(imn, v.argmin(1) + j)):
                 return False
     for ex in GOLD["two_d"]:
         a = np.array(ex["a"], np.float64)
