@@ -71,6 +71,22 @@ int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max
                   void* d_min, void* stream);
 
 /*
+ * maxmin_argfilter -- one series: the window max and min (as maxmin_filter)
+ * and their locations (Section 5: an implementation that stores locations
+ * gives the arg max/min filter at no extra cost).  Ties: the LEFTMOST
+ * location of the window's max, and of its min.
+ *   d_argmax, d_argmin : n_out int64 each, 0-based positions in d_in.
+ * w <= 1024 runs the tile kernel with (value, location) pairs; longer
+ * windows add doubling steps (window p from two overlapping windows of
+ * ceil(p/2)) through library scratch of 2 x n x (2 s + 16) bytes, grown
+ * outside graph capture (EBUSY inside one).
+ * Errors: EINVAL if w < 1, n < 0, or a pointer is null or misaligned while
+ * n_out > 0; ENOMEM if the scratch cannot be allocated.
+ */
+int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max, void* d_min,
+                     int64_t* d_argmax, int64_t* d_argmin, void* stream);
+
+/*
  * maxmin_filter_batched -- S independent series in one packed buffer, each
  * with its own window (Section 1 definition applied per series).
  *   d_in_offsets [S+1] : series k is d_in[d_in_offsets[k] .. d_in_offsets[k+1]),

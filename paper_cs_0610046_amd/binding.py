@@ -41,6 +41,7 @@ def lib():
         i64, vp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.maxmin_filter.argtypes = [ci, vp, i64, i64, vp, vp, vp]
+        L.maxmin_argfilter.argtypes = [ci, vp, i64, i64, vp, vp, vp, vp, vp]
         L.maxmin_filter_batched.argtypes = [ci, vp, vp, vp, vp, i64, vp, vp, vp]
         L.maxmin_out_offsets.argtypes = [vp, vp, i64, vp]
         L.maxmin_stream_create.argtypes = [ci, i64, ctypes.POINTER(vp)]
@@ -71,7 +72,7 @@ def lib():
             getattr(L, f).restype = ci
         L.maxmin_last_error.restype = ctypes.c_char_p
         L.maxmin_version.restype = ctypes.c_char_p
-        for f in ("maxmin_filter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
+        for f in ("maxmin_filter", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
                   "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_set_strategy",
                   "maxmin_plan", "maxmin_check_stream"):
             getattr(L, f).restype = ci
@@ -136,6 +137,21 @@ def maxmin_filter(x, w, out_max=None, out_min=None, stream=None):
     _check(lib().maxmin_filter(dtype_code(x.dtype), _ptr(x), x.numel(), int(w), _ptr(out_max), _ptr(out_min),
                                _stream(stream)))
     return out_max, out_min
+
+
+def maxmin_argfilter(x, w, out_max=None, out_min=None, out_argmax=None, out_argmin=None, stream=None):
+    """Window max and min of the 1-D tensor x with the leftmost location of
+    each (int64 positions in x).  Returns (max, min, argmax, argmin)."""
+    import torch
+    _cuda_1d(x, "x")
+    k = n_out(x.numel(), w)
+    out_max = torch.empty(k, dtype=x.dtype, device=x.device) if out_max is None else out_max
+    out_min = torch.empty(k, dtype=x.dtype, device=x.device) if out_min is None else out_min
+    out_argmax = torch.empty(k, dtype=torch.int64, device=x.device) if out_argmax is None else out_argmax
+    out_argmin = torch.empty(k, dtype=torch.int64, device=x.device) if out_argmin is None else out_argmin
+    _check(lib().maxmin_argfilter(dtype_code(x.dtype), _ptr(x), x.numel(), int(w), _ptr(out_max), _ptr(out_min),
+                                  _ptr(out_argmax), _ptr(out_argmin), _stream(stream)))
+    return out_max, out_min, out_argmax, out_argmin
 
 
 def maxmin_out_offsets(in_offsets, windows):

@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 #include <tuple>
 #include <utility>
 
@@ -213,12 +214,12 @@ int ensure_batch(Workspace* ws, int64_t S) {
 
 int ensure_tmp(Workspace* ws, size_t bytes) {
   if (ws->tmp && ws->tmp_bytes >= bytes) return MAXMIN_OK;
-  int r = grow_guard(ws, "2-D intermediate images");
+  int r = grow_guard(ws, "scratch buffers");
   if (r) return r;
   if (ws->tmp) hipFree(ws->tmp);
   ws->tmp = nullptr;
   hipError_t e = hipMalloc(&ws->tmp, bytes);
-  if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(2-D intermediate, %zu B): %s", bytes, hipGetErrorString(e));
+  if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(scratch, %zu B): %s", bytes, hipGetErrorString(e));
   ws->tmp_bytes = bytes;
   return MAXMIN_OK;
 }
@@ -341,6 +342,64 @@ int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max
   a.omax = d_max;
   a.omin = d_min;
   return run_series(dtype, a, (hipStream_t)stream, "maxmin_filter");
+}
+
+int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max, void* d_min, int64_t* d_argmax,
+                     int64_t* d_argmin, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_argfilter: unknown dtype %d", dtype);
+  if (w < 1) return fail(MAXMIN_EINVAL, "maxmin_argfilter: window w=%lld < 1", (long long)w);
+  if (n < 0) return fail(MAXMIN_EINVAL, "maxmin_argfilter: n=%lld < 0", (long long)n);
+  if (n < w) return ok();  // no complete window
+  if (!d_in || !d_max || !d_min || !d_argmax || !d_argmin) return fail(MAXMIN_EINVAL, "maxmin_argfilter: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s) || !aligned(d_argmax, 8) || !aligned(d_argmin, 8))
+    return fail(MAXMIN_EINVAL, "maxmin_argfilter: pointer not aligned to the element size");
+  hipStream_t st = (hipStream_t)stream;
+  // windows: w, ceil(w/2), ... down to the first one the tile kernel takes
+  std::vector<int64_t> chain{w};
+  while (chain.back() > mm::kTileMaxW) chain.push_back((chain.back() + 1) / 2);
+  std::reverse(chain.begin(), chain.end());
+  const int L = (int)chain.size() - 1;  // doubling steps
+  // level buffers: values (max, min) and locations (max, min), two sets
+  char* set[2] = {nullptr, nullptr};
+  const size_t set_bytes = (size_t)n * (2 * s + 2 * sizeof(int64_t));
+  if (L > 0) {
+    Workspace* ws = nullptr;
+    int r = get_ws(st, &ws);
+    if (r) return r;
+    if ((r = ensure_tmp(ws, (L > 1 ? 2 : 1) * set_bytes))) return r;
+    set[0] = (char*)ws->tmp;
+    set[1] = (char*)ws->tmp + (L > 1 ? set_bytes : 0);
+  }
+  auto vx = [&](int k) -> void* { return set[k]; };
+  auto vn = [&](int k) -> void* { return set[k] + (size_t)n * s; };
+  auto ix = [&](int k) -> int64_t* { return (int64_t*)(set[k] + (size_t)n * 2 * s); };
+  auto in = [&](int k) -> int64_t* { return (int64_t*)(set[k] + (size_t)n * (2 * s + sizeof(int64_t))); };
+  // level 0: the tile kernel with locations
+  JobArgs a;
+  a.mode = 0;
+  a.a = d_in;
+  a.na = n;
+  a.n = n;
+  a.w = chain[0];
+  a.omax = L ? vx(0) : d_max;
+  a.omin = L ? vn(0) : d_min;
+  a.amax = L ? ix(0) : d_argmax;
+  a.amin = L ? in(0) : d_argmin;
+  const int cap = mm::grid_cap(dtype, mm::kStratArg);
+  a.run = mm::run_length(n - a.w + 1, cap);
+  a.ntiles = mm::run_count(n, a.w, a.run);
+  hipError_t e = mm::launch_1d(dtype, mm::kStratArg, a, (int)std::min<int64_t>(a.ntiles, cap), st);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter");
+  for (int l = 1; l <= L; ++l) {
+    const int src = (l - 1) & 1, dst = l & 1;
+    const bool last = l == L;
+    e = mm::launch_arg_combine(dtype, vx(src), vn(src), ix(src), in(src), chain[l] - chain[l - 1], n - chain[l] + 1,
+                               last ? d_max : vx(dst), last ? d_min : vn(dst), last ? d_argmax : ix(dst),
+                               last ? d_argmin : in(dst), st);
+    if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter (doubling)");
+  }
+  return ok();
 }
 
 int maxmin_out_offsets(const int64_t* h_in_offsets, const int64_t* h_windows, int64_t S, int64_t* h_out_offsets) {

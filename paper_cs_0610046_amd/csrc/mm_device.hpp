@@ -30,11 +30,33 @@ template <> struct Lim<uint16_t> {
 template <class T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
 template <class T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
 
+// A value with its location (relative to a known origin), for the arg
+// max/min filter.  Selection orders by value, then prefers the smaller
+// location, so every combine returns the leftmost extremum whatever the
+// operand order: the result is the same for any grouping of the scans.
+template <class T> struct Loc {
+  T v;
+  int i;
+};
+template <class T> __device__ __forceinline__ Loc<T> vmax(Loc<T> a, Loc<T> b) {
+  return (a.v > b.v || (a.v == b.v && a.i < b.i)) ? a : b;
+}
+template <class T> __device__ __forceinline__ Loc<T> vmin(Loc<T> a, Loc<T> b) {
+  return (a.v < b.v || (a.v == b.v && a.i < b.i)) ? a : b;
+}
+// an element of the tile kernel: the value, or the value and its location
+template <class T, bool ARG> struct ElemOf { typedef T type; };
+template <class T> struct ElemOf<T, true> { typedef Loc<T> type; };
+template <class T> __device__ __forceinline__ T elem(T v, int, T*) { return v; }
+template <class T> __device__ __forceinline__ Loc<T> elem(T v, int i, Loc<T>*) { return Loc<T>{v, i}; }
+template <class T> __device__ __forceinline__ T value_of(T e) { return e; }
+template <class T> __device__ __forceinline__ T value_of(Loc<T> e) { return e.v; }
+
 // ---------------------------------------------------------------- LDS layout
 // One pad element per 128 bytes: a thread reading V consecutive elements and
 // a wave writing lane-consecutive elements both stay clear of bank conflicts.
 template <class T> struct Pad {
-  static constexpr int sh = sizeof(T) == 8 ? 4 : (sizeof(T) == 4 ? 5 : 6);
+  static constexpr int sh = sizeof(T) == 16 ? 3 : (sizeof(T) == 8 ? 4 : (sizeof(T) == 4 ? 5 : 6));
 };
 template <class T> __host__ __device__ constexpr int lds_idx(int i) { return i + (i >> Pad<T>::sh); }
 template <class T> __host__ __device__ constexpr int lds_len(int n) { return n + (n >> Pad<T>::sh) + 1; }
@@ -51,6 +73,12 @@ template <class T> __device__ __forceinline__ T shdn(T v, unsigned d, int width)
 }
 template <> __device__ __forceinline__ uint16_t shdn<uint16_t>(uint16_t v, unsigned d, int width) {
   return (uint16_t)__shfl_down((unsigned)v, d, width);
+}
+template <class T> __device__ __forceinline__ Loc<T> shup(Loc<T> v, unsigned d, int width) {
+  return Loc<T>{shup(v.v, d, width), __shfl_up(v.i, d, width)};
+}
+template <class T> __device__ __forceinline__ Loc<T> shdn(Loc<T> v, unsigned d, int width) {
+  return Loc<T>{shdn(v.v, d, width), __shfl_down(v.i, d, width)};
 }
 
 // ---------------------------------------------------------------- DPP
@@ -215,6 +243,8 @@ template <class T> struct Job {
   int64_t ld_out;
   int64_t tpr;            // rows: tiles per row
   int64_t run;            // tile strategy: windows per run (a multiple of the sub-tile)
+  int64_t* amax;          // arg filter (single series, tile strategy): locations of the
+  int64_t* amin;          //   leftmost max / min of every window, else null
   int ranges;             // chunk strategy, single series: ticket ranges (0: one counter)
   FlagRing ring;          // chunk strategy only
   Ctl* ctl;

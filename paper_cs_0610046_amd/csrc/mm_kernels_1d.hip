@@ -282,8 +282,15 @@ __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_
   }
 }
 
-template <class T>
-__device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t R1, TileLds<T>& sm) {
+// ARG: also the leftmost location of every window's max and min (values
+// travel with their location relative to R0; outputs amax/amin get R0 +
+// location, the position in the series).
+template <class T, bool ARG>
+__device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t R1,
+                                         TileLds<typename ElemOf<T, ARG>::type>& sm, int64_t* amax,
+                                         int64_t* amin) {
+  typedef typename ElemOf<T, ARG>::type E;
+  E* const et = nullptr;  // selects elem()'s overload
   constexpr int NT = kTileThreads, V = kTileV, TT = kTileOut, RING = 2 * kTileOut;
   const int tid = threadIdx.x;
   const int w = (int)s.w;
@@ -306,7 +313,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   const bool last_run = R1 == nout;
 
   T cur[V], nxt[V];
-  T sx[V], sn[V];  // SUF of the previous sub-tile's positions
+  E sx[V], sn[V];  // SUF of the previous sub-tile's positions
   run_load<T>(s, vbase, din, R0 + tid * V, lim, cur);
   for (int k = 0; k < nsub; ++k) {
     const int pr0 = k * TT + tid * V;  // position of cur[0], relative to R0
@@ -321,26 +328,27 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     }
     // PRE of P_k into the ring
     {
-      T px[V], pn[V];
-      px[0] = cur[0];
-      pn[0] = cur[0];
+      E px[V], pn[V];
+      px[0] = elem(cur[0], pr0, et);
+      pn[0] = px[0];
 #pragma unroll
       for (int i = 1; i < V; ++i) {
         const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
-        px[i] = start ? cur[i] : vmax(px[i - 1], cur[i]);
-        pn[i] = start ? cur[i] : vmin(pn[i - 1], cur[i]);
+        const E c = elem(cur[i], pr0 + i, et);
+        px[i] = start ? c : vmax(px[i - 1], c);
+        pn[i] = start ? c : vmin(pn[i - 1], c);
       }
       if (m > 1) {
         // a block spans m aligned lanes: exclusive scan of the lane totals
-        T ix = px[V - 1], in = pn[V - 1];
+        E ix = px[V - 1], in = pn[V - 1];
         for (int d = 1; d < m; d <<= 1) {
-          const T a = shup(ix, d, m), b = shup(in, d, m);
+          const E a = shup(ix, d, m), b = shup(in, d, m);
           if (lig >= d) {
             ix = vmax(ix, a);
             in = vmin(in, b);
           }
         }
-        const T cx = shup(ix, 1, m), cn = shup(in, 1, m);
+        const E cx = shup(ix, 1, m), cn = shup(in, 1, m);
         if (lig > 0) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
@@ -352,30 +360,31 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       const int slot = pr0 & (RING - 1);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        sm.pm[lds_idx<T>(slot + i)] = px[i];
-        sm.pn[lds_idx<T>(slot + i)] = pn[i];
+        sm.pm[lds_idx<E>(slot + i)] = px[i];
+        sm.pn[lds_idx<E>(slot + i)] = pn[i];
       }
     }
     // SUF of P_k, kept for the next sub-tile's outputs
-    T ux[V], un[V];
-    ux[V - 1] = cur[V - 1];
-    un[V - 1] = cur[V - 1];
+    E ux[V], un[V];
+    ux[V - 1] = elem(cur[V - 1], pr0 + V - 1, et);
+    un[V - 1] = ux[V - 1];
 #pragma unroll
     for (int i = V - 2; i >= 0; --i) {
       const bool end = ((pr0 + i + 1) & (B - 1)) == 0;  // a block ends here
-      ux[i] = end ? cur[i] : vmax(ux[i + 1], cur[i]);
-      un[i] = end ? cur[i] : vmin(un[i + 1], cur[i]);
+      const E c = elem(cur[i], pr0 + i, et);
+      ux[i] = end ? c : vmax(ux[i + 1], c);
+      un[i] = end ? c : vmin(un[i + 1], c);
     }
     if (m > 1) {
-      T jx = ux[0], jn = un[0];
+      E jx = ux[0], jn = un[0];
       for (int d = 1; d < m; d <<= 1) {
-        const T a = shdn(jx, d, m), b = shdn(jn, d, m);
+        const E a = shdn(jx, d, m), b = shdn(jn, d, m);
         if (lig + d < m) {
           jx = vmax(jx, a);
           jn = vmin(jn, b);
         }
       }
-      const T cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
+      const E cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
       if (lig < m - 1) {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -389,23 +398,38 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       // windows starting in P_{k-1}: SUF (registers), PRE at the window end
       // and the whole block strictly inside, if any (both from the ring)
       const int qr0 = pr0 - TT;
-      T ox[V], on[V];
+      E ox[V], on[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const int q = qr0 + i, e = q + w - 1;
-        T rx = vmax(sx[i], sm.pm[lds_idx<T>(e & (RING - 1))]);
-        T rn = vmin(sn[i], sm.pn[lds_idx<T>(e & (RING - 1))]);
+        E rx = vmax(sx[i], sm.pm[lds_idx<E>(e & (RING - 1))]);
+        E rn = vmin(sn[i], sm.pn[lds_idx<E>(e & (RING - 1))]);
         const int b1 = q >> lgB, b2 = e >> lgB;
         if (b2 >= b1 + 2) {
           const int mi = (((b1 + 2) << lgB) - 1) & (RING - 1);
-          rx = vmax(rx, sm.pm[lds_idx<T>(mi)]);
-          rn = vmin(rn, sm.pn[lds_idx<T>(mi)]);
+          rx = vmax(rx, sm.pm[lds_idx<E>(mi)]);
+          rn = vmin(rn, sm.pn[lds_idx<E>(mi)]);
         }
         ox[i] = rx;
         on[i] = rn;
       }
       const int64_t q0 = R0 + qr0;
-      run_store<T>(s.omax + q0, s.omin + q0, ovec, dmx, q0, R1, ox, on);
+      if constexpr (ARG) {
+        T vx[V], vn[V];
+        int64_t lx[V], ln[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          vx[i] = ox[i].v;
+          vn[i] = on[i].v;
+          lx[i] = R0 + ox[i].i;
+          ln[i] = R0 + on[i].i;
+        }
+        run_store<T>(s.omax + q0, s.omin + q0, ovec, dmx, q0, R1, vx, vn);
+        const int lmx = (int)(((uintptr_t)(amax + R0) / 8) & 1), lmn = (int)(((uintptr_t)(amin + R0) / 8) & 1);
+        run_store<int64_t>(amax + q0, amin + q0, lmx == lmn, lmx, q0, R1, lx, ln);
+      } else {
+        run_store<T>(s.omax + q0, s.omin + q0, ovec, dmx, q0, R1, ox, on);
+      }
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
@@ -419,16 +443,16 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
 
 // Persistent: static round-robin over runs (runs share no data beyond a
 // w-1 halo; on MI355X this beat the XCD-contiguous schedule by ~2%).
-template <int MODE, class T>
+template <int MODE, class T, bool ARG = false>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
-  __shared__ TileLds<T> sm;
+  __shared__ TileLds<typename ElemOf<T, ARG>::type> sm;
   const int64_t nruns = job_tiles<MODE>(job);
   for (int64_t t = blockIdx.x; t < nruns; t += gridDim.x) {
     int64_t local, gbase;
     const Series<T> s = job_series<MODE>(job, t, local, gbase);
     const int64_t nout = s.n - s.w + 1;
     const int64_t R0 = local * job.run;
-    run_body<T>(s, R0, min(nout, R0 + job.run), sm);
+    run_body<T, ARG>(s, R0, min(nout, R0 + job.run), sm, job.amax, job.amin);
   }
 }
 
@@ -801,6 +825,31 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   }
 }
 
+// ================================================ arg filter, long windows
+// A window [j, j+p) is the union of [j, j+q) and [j+p-q, j+p) when
+// p <= 2q, so its leftmost max (min) is the leftmost of the two shorter
+// windows' results: one doubling step maps the (value, location) outputs of
+// window q to those of window p.  Used for windows longer than the tile
+// kernel takes (w > kTileMaxW), starting from a tile-kernel pass.
+template <class T>
+__global__ __launch_bounds__(256) void k_argcombine(const T* __restrict__ vx, const T* __restrict__ vn,
+                                                    const int64_t* __restrict__ ix, const int64_t* __restrict__ in_,
+                                                    int64_t d, int64_t nout, T* __restrict__ ox, T* __restrict__ on,
+                                                    int64_t* __restrict__ jx, int64_t* __restrict__ jn) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nout; j += stride) {
+    const T a = gload(vx + j), b = gload(vx + j + d), c = gload(vn + j), e = gload(vn + j + d);
+    const int64_t la = gload(ix + j), lb = gload(ix + j + d), lc = gload(in_ + j), le = gload(in_ + j + d);
+    // equal values: the smaller location wins (both lie in the window)
+    const bool ta = a > b || (a == b && la <= lb);
+    const bool tc = c < e || (c == e && lc <= le);
+    gstore(ox + j, ta ? a : b);
+    gstore(jx + j, ta ? la : lb);
+    gstore(on + j, tc ? c : e);
+    gstore(jn + j, tc ? lc : le);
+  }
+}
+
 // ============================================ chunk runs (local aggregates)
 // Same window-aligned chunks as above (at most kCrMax inputs), but a
 // workgroup walks a run of consecutive chunks of one series and keeps the
@@ -1109,6 +1158,8 @@ template <class T> static Job<T> make_job(const JobArgs& a) {
   j.ld_out = a.ld_out;
   j.tpr = a.tpr;
   j.run = a.run;
+  j.amax = a.amax;
+  j.amin = a.amin;
   j.ranges = a.ranges;
   j.ring.f = a.ring;
   j.ring.lg = a.ring_lg;
@@ -1135,14 +1186,15 @@ template <class K> static int occupancy_grid(K kernel, int threads) {
 }
 
 int grid_cap(int dtype, int strategy) {
-  static int cap[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratRun) return 0;
+  static int cap[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratArg) return 0;
   int& c = cap[strategy - 1][dtype];
   if (!c) {
     (void)dispatch(dtype, [&](auto* p) {
       using T = std::remove_pointer_t<decltype(p)>;
       c = strategy == kStratTile    ? occupancy_grid(k_tile<kJobDescs, T>, kTileThreads)
           : strategy == kStratChunk ? occupancy_grid(k_chunk<kJobDescs, T>, kChunkThreads)
+          : strategy == kStratArg   ? occupancy_grid(k_tile<kJobOne, T, true>, kTileThreads)
                                     : occupancy_grid(k_crun<kJobDescs, T>, kChunkThreads);
       return hipSuccess;
     });
@@ -1155,7 +1207,10 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
     using T = std::remove_pointer_t<decltype(p)>;
     const Job<T> j = make_job<T>(a);
     const dim3 g(grid);
-    if (strategy == kStratTile) {
+    if (strategy == kStratArg) {
+      if (a.mode != kJobOne || a.amax == nullptr || a.amin == nullptr) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_tile<kJobOne, T, true>), g, dim3(kTileThreads), 0, st, j);
+    } else if (strategy == kStratTile) {
       if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T>), g, dim3(kTileThreads), 0, st, j);
       else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_tile<kJobDescs, T>), g, dim3(kTileThreads), 0, st, j);
       else hipLaunchKernelGGL((k_tile<kJobRows, T>), g, dim3(kTileThreads), 0, st, j);
@@ -1179,6 +1234,18 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
     using T = std::remove_pointer_t<decltype(p)>;
     hipLaunchKernelGGL(k_batched_setup<T>, dim3(1), dim3(1024), 0, st, (const T*)d_in, in_off, wins, out_off, S,
                        (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk, (int64_t)kRunBatched);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,
+                              int64_t d, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn, hipStream_t st) {
+  if (nout <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((nout + 255) / 256, (int64_t)cu_count() * 16);
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    hipLaunchKernelGGL(k_argcombine<T>, dim3(grid), dim3(256), 0, st, (const T*)vx, (const T*)vn, ix, in_, d, nout,
+                       (T*)ox, (T*)on, jx, jn);
     return hipGetLastError();
   });
 }

@@ -87,6 +87,8 @@ struct JobArgs {
   int64_t ld_out = 0;
   int64_t tpr = 0;
   int64_t run = 0;  // tile strategy: windows per run
+  int64_t* amax = nullptr;  // arg filter outputs (single series, tile strategy only)
+  int64_t* amin = nullptr;
   int ranges = 0;   // chunk strategy, single series: ticket ranges (0 or 1: one counter)
   // chunk strategy look-back state
   uint64_t* ring = nullptr;
@@ -94,7 +96,8 @@ struct JobArgs {
   Ctl* ctl = nullptr;
 };
 
-enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3 };
+// kStratArg: the tile kernel carrying locations (arg max/min filter).
+enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3, kStratArg = 4 };
 
 // Occupancy-derived persistent grid sizes (computed once per device).
 int grid_cap(int dtype, int strategy);
@@ -110,6 +113,10 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
 // A stream push that completes no window: new carry = last min(n, w-1)
 // samples of (a[0..na) ++ b).
 hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st);
+// One doubling step of the arg filter (see k_argcombine): outputs j < nout
+// from inputs j and j + d of the shorter window's value/location arrays.
+hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,
+                              int64_t d, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn, hipStream_t st);
 
 size_t series_bytes();
 

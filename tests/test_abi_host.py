@@ -31,7 +31,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ("maxmin_filter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
+    for n in ("maxmin_filter", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
               "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_last_error"):
         assert n in names
 
@@ -59,6 +59,12 @@ def test_argument_errors_without_gpu(lib):
     assert lib.maxmin_filter_batched(0, None, None, None, None, 0, None, None, None) == binding.MAXMIN_OK
     assert lib.maxmin_filter_2d(0, None, 5, 5, 4, 2, 2, None, None, 4, None) == binding.MAXMIN_EINVAL  # ld < cols
     assert lib.maxmin_filter_2d(0, None, 5, 5, 5, 6, 2, None, None, 4, None) == binding.MAXMIN_OK  # no output
+    assert lib.maxmin_argfilter(0, None, 10, 0, None, None, None, None, None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_argfilter(0, None, 10, 11, None, None, None, None, None) == binding.MAXMIN_OK
+    assert lib.maxmin_argfilter(0, vp(0x1000), 10, 3, vp(0x2000), vp(0x3000), None, vp(0x4000), None) == \
+        binding.MAXMIN_EINVAL
+    assert lib.maxmin_argfilter(0, vp(0x1000), 10, 3, vp(0x2000), vp(0x3000), vp(0x4004), vp(0x5000), None) == \
+        binding.MAXMIN_EINVAL  # location output not 8-byte aligned
     assert lib.maxmin_set_strategy(9) == binding.MAXMIN_EINVAL
     assert lib.maxmin_set_strategy(3) == binding.MAXMIN_OK
     assert lib.maxmin_set_strategy(0) == binding.MAXMIN_OK

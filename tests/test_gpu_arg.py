@@ -1,0 +1,116 @@
+"""GPU parity of the arg max/min filter (leftmost locations) against the
+oracle: values bit-exact against the wedge, locations exact against the
+linear-time deque (itself pinned to the definition), over every dtype, tie-
+heavy and smooth inputs, windows served by the tile kernel and by doubling
+steps, ragged sizes and misaligned buffers; at n = 2^28, sampled windows
+against the definition plus whole-array properties."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0610046_amd import binding as mm
+from paper_cs_0610046_amd import synth
+from gpu_util import assert_bits_equal, note, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+DTS = [np.float32, np.float64, np.int32, np.uint16]
+WINDOWS = [1, 2, 3, 7, 8, 9, 16, 63, 64, 65, 255, 256, 511, 512, 513, 1000, 1024, 1025, 1500, 2048, 2049,
+           4097, 10000, 70000]
+
+
+def _data(n, dt, rng, ties):
+    if ties:
+        return synth.small_alphabet(n, 5, dt, rng)
+    if dt in (np.float32, np.float64):
+        return synth.random_walk(n, dt, rng)
+    return synth.small_alphabet(n, 60000 if dt == np.uint16 else 1 << 30, dt, rng)
+
+
+def _check(a, w, what, off=(0, 0, 0, 0, 0)):
+    import torch
+    oi, ox, on, ix, ino = off
+    n = a.size
+    no = max(0, n - w + 1)
+    buf = to_dev(np.concatenate([np.zeros(oi, a.dtype), a]))
+    tdt = buf.dtype
+    bmx = torch.empty(no + 8, dtype=tdt, device="cuda")
+    bmn = torch.empty(no + 8, dtype=tdt, device="cuda")
+    bix = torch.empty(no + 8, dtype=torch.int64, device="cuda")
+    bin_ = torch.empty(no + 8, dtype=torch.int64, device="cuda")
+    mm.maxmin_argfilter(buf[oi:], w, bmx[ox:ox + no], bmn[on:on + no], bix[ix:ix + no], bin_[ino:ino + no])
+    torch.cuda.synchronize()
+    mm.maxmin_check_stream()
+    if no == 0:
+        return
+    emx, emn = oracle.wedge(a, w)
+    eix, ein = oracle.argdeque(a, w)
+    assert_bits_equal(to_host(bmx[ox:ox + no], a.dtype), emx, what + " max")
+    assert_bits_equal(to_host(bmn[on:on + no], a.dtype), emn, what + " min")
+    gix = bix[ix:ix + no].cpu().numpy()
+    gin = bin_[ino:ino + no].cpu().numpy()
+    bad = np.flatnonzero(gix != eix)
+    assert bad.size == 0, "%s argmax: %d mismatches, first at %d: got %d want %d" % (what, bad.size, bad[0], gix[bad[0]], eix[bad[0]])
+    bad = np.flatnonzero(gin != ein)
+    assert bad.size == 0, "%s argmin: %d mismatches, first at %d: got %d want %d" % (what, bad.size, bad[0], gin[bad[0]], ein[bad[0]])
+
+
+@pytest.mark.parametrize("dt", DTS, ids=lambda d: np.dtype(d).name)
+def test_argfilter_windows(dt):
+    rng = synth.rng_for("tests", 500)
+    for w in WINDOWS:
+        for n in sorted({w, w + 1, 2 * w + 3, 40001, 2048 + w - 1, 4096 * 3 + w + 11}):
+            for ties in (True, False):
+                a = _data(n, dt, rng, ties)
+                note("arg dt=%s n=%d w=%d ties=%s" % (np.dtype(dt).name, n, w, ties))
+                _check(a, w, "n=%d w=%d ties=%s" % (n, w, ties))
+
+
+def test_argfilter_small_and_degenerate():
+    rng = synth.rng_for("tests", 501)
+    for dt in DTS:
+        for n, w in [(1, 1), (2, 1), (2, 2), (3, 2), (5, 5), (1, 2), (0, 1), (10, 11), (3000, 3000), (3001, 2999)]:
+            a = _data(n, dt, rng, True)
+            note("arg degenerate dt=%s n=%d w=%d" % (np.dtype(dt).name, n, w))
+            _check(a, w, "n=%d w=%d" % (n, w))
+        # constant series: every window's first location, for both
+        a = np.full(9000, 7, dt)
+        _check(a, 300, "constant")
+
+
+def test_argfilter_misaligned():
+    rng = synth.rng_for("tests", 502)
+    for dt in DTS:
+        for off in ((1, 2, 3, 1, 0), (3, 1, 1, 0, 1), (5, 7, 6, 1, 1), (2, 0, 0, 0, 0)):
+            for w in (3, 300, 3000):
+                a = _data(70001, dt, rng, w != 300)
+                note("arg misaligned dt=%s off=%s w=%d" % (np.dtype(dt).name, off, w))
+                _check(a, w, "offsets %s w=%d" % (off, w), off=off)
+
+
+@pytest.mark.timeout(600)
+def test_argfilter_full_size_sampled():
+    """n = 2^28 float32 walk at windows 256 and 4096 (a doubling step):
+    sampled windows against the definition (numpy's first-occurrence argmax
+    over the window), every location inside its window, and the values at
+    the locations equal to the max/min outputs."""
+    import torch
+    n = 1 << 28
+    a = synth.large_series("walk", n)
+    x = to_dev(a)
+    rng = np.random.default_rng(7)
+    for w in (256, 4096):
+        note("arg full size w=%d" % w)
+        mx, mn, ix, in_ = mm.maxmin_argfilter(x, w)
+        torch.cuda.synchronize()
+        no = n - w + 1
+        j = torch.arange(no, device="cuda", dtype=torch.int64)
+        assert bool(((ix >= j) & (ix < j + w) & (in_ >= j) & (in_ < j + w)).all())
+        assert torch.equal(x[ix], mx) and torch.equal(x[in_], mn)
+        del j
+        samp = np.concatenate([np.arange(4), rng.integers(0, no, 2000), np.arange(no - 4, no)])
+        gix, gin = ix[torch.from_numpy(samp).cuda()].cpu().numpy(), in_[torch.from_numpy(samp).cuda()].cpu().numpy()
+        for k, s in enumerate(samp):
+            win = a[s:s + w]
+            assert gix[k] == s + int(np.argmax(win)) and gin[k] == s + int(np.argmin(win)), (w, s)
+        del mx, mn, ix, in_
