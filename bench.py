@@ -16,6 +16,7 @@ Also reported on the same JSON line (not part of ``value``):
 * ``batched``      -- 10,000 float32 random walks, lengths log-uniform in
   [1e3, 1e6], windows uniform in [2, 1024], one batched call (graph replay),
 * ``image``        -- 8192 x 8192 float32, w x w windows, rows then columns,
+* ``argfilter``    -- n = 2**28 float32 walk, values plus leftmost locations,
 * ``cpu_baseline`` -- the CPU oracle (single thread) on a bounded sample.
 """
 import argparse
@@ -272,6 +273,24 @@ def run_extras(torch, mm, synth, dev, stream):
     out["image"] = {"workload": "8192x8192 float32 Gaussian field + noise, rows then columns", "per_window": res}
     print("[bench] image done", file=sys.stderr, flush=True)
     del xi
+
+    # arg filter: n = 2^28 float32 walk, values and leftmost locations
+    xa = torch.from_numpy(synth.random_walk(1 << 28, np.float32, synth.rng_for("large", 0))).to(dev)
+    res = {}
+    for w in (256, 4096):
+        outs = mm.maxmin_argfilter(xa, w)
+        mm.maxmin_argfilter(xa, w, *outs)
+        ts = timed(lambda: mm.maxmin_argfilter(xa, w, *outs), 5, stream)
+        ms = float(np.median(ts))
+        ab = xa.numel() * 4 + outs[0].numel() * (2 * 4 + 2 * 8)
+        res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(xa.numel() / (ms * 1e-3) / 1e9, 2),
+                       "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
+                       "path": "tile with locations" if w <= 1024 else "tile + doubling steps"}
+        del outs
+    out["argfilter"] = {"workload": "n=2^28 float32 walk; max, min and their leftmost int64 locations "
+                                    "(algorithmic bytes: 4 read + 24 written per window)", "per_window": res}
+    print("[bench] argfilter done", file=sys.stderr, flush=True)
+    del xa
 
     # serving: Poisson filter requests + 1000 persistent streams, 64 GB budget
     from paper_cs_0610046_amd.serving import serving_run
