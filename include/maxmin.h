@@ -64,8 +64,12 @@ typedef enum {
 /*
  * maxmin_filter -- one series (Section 1 definition).
  *   d_in  : n elements of `dtype`, contiguous.
- *   d_max, d_min : n_out = max(0, n-w+1) elements each, contiguous.
- * Errors: EINVAL if w < 1, n < 0, or a pointer is null while n_out > 0.
+ *   d_max, d_min : n_out = max(0, n-w+1) elements each, contiguous.  One of
+ *                  them may be NULL: a max-only or min-only filter (that
+ *                  output is neither computed into memory nor stored).
+ *                  The same holds for the batched, stream and 2-D calls.
+ * Errors: EINVAL if w < 1, n < 0, or d_in (or both outputs) is null while
+ * n_out > 0.
  */
 int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max,
                   void* d_min, void* stream);
@@ -153,6 +157,31 @@ int64_t maxmin_stream_samples(const maxmin_stream_t* st);
 int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int64_t ld_in,
                      int64_t w_rows, int64_t w_cols, void* d_max, void* d_min, int64_t ld_out,
                      void* stream);
+
+/* Grey-scale morphology operators of maxmin_morph_2d. */
+typedef enum {
+  MAXMIN_ERODE = 0,  /* min over the rectangle (the min half of maxmin_filter_2d) */
+  MAXMIN_DILATE = 1, /* max over the rectangle */
+  MAXMIN_OPEN = 2,   /* dilation of the erosion */
+  MAXMIN_CLOSE = 3   /* erosion of the dilation */
+} maxmin_morph_t;
+
+/*
+ * maxmin_morph_2d -- erosion, dilation, opening or closing of an image with
+ * a w_rows x w_cols rectangle (Section 1: the filter's image-processing use,
+ * applied to rows then columns), valid windows only.
+ *   erode / dilate : output (rows-w_rows+1) x (cols-w_cols+1);
+ *   open / close   : output (rows-2*w_rows+2) x (cols-2*w_cols+2) (two
+ *                    filters; the intermediate image lives in library
+ *                    scratch, grown outside graph capture).
+ *   d_out : leading dimension ld_out (elements), caller-owned.
+ * Errors: EINVAL for an unknown op, a window < 1, negative sizes,
+ * ld_in < cols, ld_out < output width, or a null / misaligned pointer with
+ * work to do; ENOMEM if scratch cannot be allocated.
+ */
+int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int64_t ld_in,
+                    int64_t w_rows, int64_t w_cols, int op, void* d_out, int64_t ld_out,
+                    void* stream);
 
 /*
  * Serving engine -- many callers submit filter requests and stream chunks

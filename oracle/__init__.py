@@ -12,7 +12,8 @@ Comparisons per Element".
 * :func:`wedge` / :class:`Stream` -- the paper's streaming monotonic-wedge
   algorithm (Section 4, Algorithm 1), with value-comparison counting.
 * :func:`filter2d` -- rows first, then columns (Section 1); :func:`naive2d`
-  -- the 2-D rectangle definition.
+  -- the 2-D rectangle definition; :func:`morph2d` -- erosion, dilation,
+  opening and closing as compositions of the 2-D filter.
 * :func:`batched` / :func:`out_offsets` -- one filter per series of a packed
   buffer (independent series; the per-series call is the 1-D oracle).
 * :func:`argnaive` -- the leftmost location of each window's max and min,
@@ -25,7 +26,7 @@ Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 invariants, hand-built worked examples and the paper's comparison bounds).
 """
 from .oracle import (DTYPES, build, load, naive, wedge, Stream, filter2d,
-                     naive2d, batched, out_offsets, n_out, argnaive, argdeque)
+                     naive2d, morph2d, batched, out_offsets, n_out, argnaive, argdeque)
 
 __all__ = ["DTYPES", "build", "load", "naive", "wedge", "Stream", "filter2d",
-           "naive2d", "batched", "out_offsets", "n_out", "argnaive", "argdeque"]
+           "naive2d", "morph2d", "batched", "out_offsets", "n_out", "argnaive", "argdeque"]

@@ -203,6 +203,24 @@ def naive2d(a, wr, wc=None):
     return _two_d(load().oracle_naive2d, a, wr, wr if wc is None else wc)
 
 
+def morph2d(a, op, wr, wc=None, filt=None):
+    """Grey-scale morphology with a wr x wc rectangle, valid windows:
+    erosion = the min image of the 2-D filter, dilation = the max image,
+    opening = dilation of the erosion, closing = erosion of the dilation.
+    ``filt`` is the 2-D filter used (default :func:`filter2d`)."""
+    wc = wr if wc is None else wc
+    filt = filt or filter2d
+    if op == "erode":
+        return filt(a, wr, wc)[1]
+    if op == "dilate":
+        return filt(a, wr, wc)[0]
+    first, second = (1, 0) if op == "open" else (0, 1)
+    mid = filt(a, wr, wc)[first]
+    if mid.size == 0:
+        return np.empty((max(0, mid.shape[0] - wr + 1), max(0, mid.shape[1] - wc + 1)), a.dtype)
+    return filt(mid, wr, wc)[second]
+
+
 def out_offsets(in_offsets, windows):
     """Exclusive scan of max(0, n_k - w_k + 1): where each series' outputs go."""
     in_offsets = np.asarray(in_offsets, np.int64)

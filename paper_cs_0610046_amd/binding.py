@@ -50,6 +50,7 @@ def lib():
         L.maxmin_stream_samples.argtypes = [vp]
         L.maxmin_stream_samples.restype = i64
         L.maxmin_filter_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, vp, vp, i64, vp]
+        L.maxmin_morph_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, ci, vp, i64, vp]
         L.maxmin_set_strategy.argtypes = [ci]
         L.maxmin_plan.argtypes = [ci, i64, i64]
         L.maxmin_check_stream.argtypes = [vp]
@@ -73,7 +74,8 @@ def lib():
         L.maxmin_last_error.restype = ctypes.c_char_p
         L.maxmin_version.restype = ctypes.c_char_p
         for f in ("maxmin_filter", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
-                  "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_set_strategy",
+                  "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_morph_2d",
+                  "maxmin_set_strategy",
                   "maxmin_plan", "maxmin_check_stream"):
             getattr(L, f).restype = ci
         _lib = L
@@ -125,15 +127,25 @@ def n_out(n, w):
     return max(0, int(n) - int(w) + 1)
 
 
-def maxmin_filter(x, w, out_max=None, out_min=None, stream=None):
-    """Running max and min of every window [j, j+w) of the 1-D tensor x."""
+def _want(which):
+    if which not in ("both", "max", "min"):
+        raise ValueError("which must be 'both', 'max' or 'min'")
+    return which != "min", which != "max"
+
+
+def maxmin_filter(x, w, out_max=None, out_min=None, stream=None, which="both"):
+    """Running max and min of every window [j, j+w) of the 1-D tensor x.
+    ``which="max"`` / ``"min"``: a max-only / min-only filter (the other
+    output is None and is not computed into memory)."""
     import torch
     _cuda_1d(x, "x")
     k = n_out(x.numel(), w)
-    if out_max is None:
+    wx, wn = _want(which)
+    if out_max is None and wx:
         out_max = torch.empty(k, dtype=x.dtype, device=x.device)
-    if out_min is None:
+    if out_min is None and wn:
         out_min = torch.empty(k, dtype=x.dtype, device=x.device)
+    out_max, out_min = (out_max if wx else None), (out_min if wn else None)
     _check(lib().maxmin_filter(dtype_code(x.dtype), _ptr(x), x.numel(), int(w), _ptr(out_max), _ptr(out_min),
                                _stream(stream)))
     return out_max, out_min
@@ -165,7 +177,8 @@ def maxmin_out_offsets(in_offsets, windows):
     return out
 
 
-def maxmin_filter_batched(packed, in_offsets, windows, out_offsets, out_max=None, out_min=None, stream=None):
+def maxmin_filter_batched(packed, in_offsets, windows, out_offsets, out_max=None, out_min=None, stream=None,
+                          which="both"):
     """S series packed in one tensor, each with its own window.
 
     ``in_offsets`` (S+1), ``windows`` (S) and ``out_offsets`` (S+1) are int64
@@ -176,10 +189,12 @@ def maxmin_filter_batched(packed, in_offsets, windows, out_offsets, out_max=None
     import torch
     _cuda_1d(packed, "packed")
     S = windows.numel()
-    if out_max is None or out_min is None:
+    wx, wn = _want(which)
+    if (out_max is None and wx) or (out_min is None and wn):
         total = int(out_offsets[-1].item()) if S else 0
         out_max = torch.empty(total, dtype=packed.dtype, device=packed.device) if out_max is None else out_max
         out_min = torch.empty(total, dtype=packed.dtype, device=packed.device) if out_min is None else out_min
+    out_max, out_min = (out_max if wx else None), (out_min if wn else None)
     _check(lib().maxmin_filter_batched(dtype_code(packed.dtype), _ptr(packed), _ptr(in_offsets), _ptr(windows),
                                        _ptr(out_offsets), S, _ptr(out_max), _ptr(out_min), _stream(stream)))
     return out_max, out_min
@@ -195,18 +210,20 @@ class MaxMinStream:
         _check(lib().maxmin_stream_create(dtype_code(dtype), self.w, ctypes.byref(h)))
         self._h = h
 
-    def push(self, chunk, out_max=None, out_min=None, stream=None):
+    def push(self, chunk, out_max=None, out_min=None, stream=None, which="both"):
         import torch
         _cuda_1d(chunk, "chunk")
         m = chunk.numel()
-        if out_max is None:
+        wx, wn = _want(which)
+        if out_max is None and wx:
             out_max = torch.empty(m, dtype=chunk.dtype, device=chunk.device)
-        if out_min is None:
+        if out_min is None and wn:
             out_min = torch.empty(m, dtype=chunk.dtype, device=chunk.device)
+        out_max, out_min = (out_max if wx else None), (out_min if wn else None)
         k = ctypes.c_int64(0)
         _check(lib().maxmin_stream_push(self._h, _ptr(chunk), m, _ptr(out_max), _ptr(out_min), ctypes.byref(k),
                                         _stream(stream)))
-        return out_max[:k.value], out_min[:k.value]
+        return (out_max[:k.value] if wx else None), (out_min[:k.value] if wn else None)
 
     @property
     def samples(self):
@@ -228,22 +245,53 @@ def maxmin_stream_create(dtype, w):
     return MaxMinStream(dtype, w)
 
 
-def maxmin_filter_2d(img, w_rows, w_cols=None, out_max=None, out_min=None, stream=None):
-    """Rows, then columns: max/min over every w_rows x w_cols rectangle."""
-    import torch
+def _check_img(img):
     if not img.is_cuda or img.dim() != 2 or img.stride(1) != 1:
         raise ValueError("img must be a 2-D CUDA tensor with unit column stride")
+
+
+def maxmin_filter_2d(img, w_rows, w_cols=None, out_max=None, out_min=None, stream=None, which="both"):
+    """Rows, then columns: max/min over every w_rows x w_cols rectangle."""
+    import torch
+    _check_img(img)
     w_cols = w_rows if w_cols is None else w_cols
     rows, cols = img.shape
     orr, occ = n_out(rows, w_rows), n_out(cols, w_cols)
-    if out_max is None:
+    wx, wn = _want(which)
+    if out_max is None and wx:
         out_max = torch.empty((orr, occ), dtype=img.dtype, device=img.device)
-    if out_min is None:
+    if out_min is None and wn:
         out_min = torch.empty((orr, occ), dtype=img.dtype, device=img.device)
-    ld_out = out_max.stride(0) if orr and occ else max(occ, 1)
+    out_max, out_min = (out_max if wx else None), (out_min if wn else None)
+    if out_max is not None and out_min is not None and orr and occ and out_max.stride(0) != out_min.stride(0):
+        raise ValueError("out_max and out_min must share one leading dimension")
+    ref = out_max if out_max is not None else out_min
+    ld_out = ref.stride(0) if orr and occ else max(occ, 1)
     _check(lib().maxmin_filter_2d(dtype_code(img.dtype), _ptr(img), rows, cols, img.stride(0) if rows else cols,
                                   int(w_rows), int(w_cols), _ptr(out_max), _ptr(out_min), ld_out, _stream(stream)))
     return out_max, out_min
+
+
+MORPH_OPS = {"erode": 0, "dilate": 1, "open": 2, "close": 3}
+
+
+def maxmin_morph_2d(img, op, w_rows, w_cols=None, out=None, stream=None):
+    """Grey-scale erosion / dilation / opening / closing with a w_rows x
+    w_cols rectangle (valid windows; opening and closing shrink twice)."""
+    import torch
+    _check_img(img)
+    w_cols = w_rows if w_cols is None else w_cols
+    code = MORPH_OPS[op] if isinstance(op, str) else int(op)
+    rows, cols = img.shape
+    k = 1 if code < 2 else 2
+    orr = max(0, rows - k * (int(w_rows) - 1))
+    occ = max(0, cols - k * (int(w_cols) - 1))
+    if out is None:
+        out = torch.empty((orr, occ), dtype=img.dtype, device=img.device)
+    ld_out = out.stride(0) if orr and occ else max(occ, 1)
+    _check(lib().maxmin_morph_2d(dtype_code(img.dtype), _ptr(img), rows, cols, img.stride(0) if rows else cols,
+                                 int(w_rows), int(w_cols), code, _ptr(out), ld_out, _stream(stream)))
+    return out
 
 
 def maxmin_set_strategy(strategy):

@@ -108,6 +108,8 @@ struct Workspace {
   int64_t pre_cap = 0;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
+  void* tmp2 = nullptr;  // morphology: the first filter's image
+  size_t tmp2_bytes = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -212,17 +214,19 @@ int ensure_batch(Workspace* ws, int64_t S) {
   return MAXMIN_OK;
 }
 
-int ensure_tmp(Workspace* ws, size_t bytes) {
-  if (ws->tmp && ws->tmp_bytes >= bytes) return MAXMIN_OK;
+int ensure_buf(Workspace* ws, void** buf, size_t* have, size_t bytes) {
+  if (*buf && *have >= bytes) return MAXMIN_OK;
   int r = grow_guard(ws, "scratch buffers");
   if (r) return r;
-  if (ws->tmp) hipFree(ws->tmp);
-  ws->tmp = nullptr;
-  hipError_t e = hipMalloc(&ws->tmp, bytes);
+  if (*buf) hipFree(*buf);
+  *buf = nullptr;
+  hipError_t e = hipMalloc(buf, bytes);
   if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(scratch, %zu B): %s", bytes, hipGetErrorString(e));
-  ws->tmp_bytes = bytes;
+  *have = bytes;
   return MAXMIN_OK;
 }
+int ensure_tmp(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp, &ws->tmp_bytes, bytes); }
+int ensure_tmp2(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp2, &ws->tmp2_bytes, bytes); }
 
 // Ticket ranges for a single-series chunk launch (0, 1, 8, 16 or 32); the
 // environment variable MAXMIN_CHUNK_RANGES overrides the default.
@@ -330,7 +334,7 @@ int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max
   if (w < 1) return fail(MAXMIN_EINVAL, "maxmin_filter: window w=%lld < 1", (long long)w);
   if (n < 0) return fail(MAXMIN_EINVAL, "maxmin_filter: n=%lld < 0", (long long)n);
   if (n < w) return ok();  // no complete window
-  if (!d_in || !d_max || !d_min) return fail(MAXMIN_EINVAL, "maxmin_filter: null pointer");
+  if (!d_in || (!d_max && !d_min)) return fail(MAXMIN_EINVAL, "maxmin_filter: null pointer");
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
     return fail(MAXMIN_EINVAL, "maxmin_filter: pointer not aligned to the element size");
   JobArgs a;
@@ -422,7 +426,7 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
   if (!s) return fail(MAXMIN_EINVAL, "maxmin_filter_batched: unknown dtype %d", dtype);
   if (S < 0) return fail(MAXMIN_EINVAL, "maxmin_filter_batched: S < 0");
   if (S == 0) return ok();
-  if (!d_in || !d_in_offsets || !d_windows || !d_out_offsets || !d_max || !d_min)
+  if (!d_in || !d_in_offsets || !d_windows || !d_out_offsets || (!d_max && !d_min))
     return fail(MAXMIN_EINVAL, "maxmin_filter_batched: null pointer");
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
     return fail(MAXMIN_EINVAL, "maxmin_filter_batched: pointer not aligned to the element size");
@@ -520,7 +524,7 @@ int maxmin_stream_push(maxmin_stream_t* st, const void* d_chunk, int64_t m, void
   if (h_n_out) *h_n_out = 0;
   if (m == 0) return ok();
   const size_t s = dsize(st->dt);
-  if (!d_chunk || (nout > 0 && (!d_max || !d_min))) return fail(MAXMIN_EINVAL, "maxmin_stream_push: null pointer");
+  if (!d_chunk || (nout > 0 && !d_max && !d_min)) return fail(MAXMIN_EINVAL, "maxmin_stream_push: null pointer");
   if (!aligned(d_chunk, s) || (nout > 0 && (!aligned(d_max, s) || !aligned(d_min, s))))
     return fail(MAXMIN_EINVAL, "maxmin_stream_push: pointer not aligned to the element size");
   JobArgs a;
@@ -568,7 +572,7 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   const int64_t orows = rows - w_rows + 1, oc = cols - w_cols + 1;
   if (orows <= 0 || oc <= 0) return ok();
   if (ld_out < oc) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: ld_out < output width");
-  if (!d_in || !d_max || !d_min) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: null pointer");
+  if (!d_in || (!d_max && !d_min)) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: null pointer");
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
     return fail(MAXMIN_EINVAL, "maxmin_filter_2d: pointer not aligned to the element size");
   if ((orows + w_rows - 1) / w_rows > 65535)
@@ -581,8 +585,8 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   const bool big = w_rows > mm::cols_max_window(dtype);
   const size_t scr = big ? (size_t)mm::cols_scratch_elems(rows, oc, w_rows) * s : 0;
   if ((r = ensure_tmp(ws, 2 * img + scr))) return r;
-  void* tmax = ws->tmp;
-  void* tmin = (char*)ws->tmp + img;
+  void* tmax = d_max ? ws->tmp : nullptr;  // a null output skips its image
+  void* tmin = d_min ? (char*)ws->tmp + img : nullptr;
   void* gscr = big ? (void*)((char*)ws->tmp + 2 * img) : nullptr;
   // row pass: every row is a series of `cols` inputs with window w_cols
   JobArgs a;
@@ -619,6 +623,40 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (columns)");
   return ok();
+}
+
+// Grey-scale morphology with a w_rows x w_cols rectangle: erosion is the
+// 2-D min filter, dilation the max filter, opening = dilation(erosion),
+// closing = erosion(dilation); valid windows throughout.
+int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int64_t ld_in, int64_t w_rows,
+                    int64_t w_cols, int op, void* d_out, int64_t ld_out, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: unknown dtype %d", dtype);
+  if (op < MAXMIN_ERODE || op > MAXMIN_CLOSE) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: unknown op %d", op);
+  if (w_rows < 1 || w_cols < 1) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: window < 1");
+  if (rows < 0 || cols < 0) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: negative size");
+  if (ld_in < cols) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: ld_in < cols");
+  if (op == MAXMIN_ERODE || op == MAXMIN_DILATE)
+    return maxmin_filter_2d(dtype, d_in, rows, cols, ld_in, w_rows, w_cols, op == MAXMIN_DILATE ? d_out : nullptr,
+                            op == MAXMIN_ERODE ? d_out : nullptr, ld_out, stream);
+  const int64_t r1 = rows - w_rows + 1, c1 = cols - w_cols + 1;
+  if (r1 - w_rows + 1 <= 0 || c1 - w_cols + 1 <= 0) return ok();  // no output
+  if (ld_out < c1 - w_cols + 1) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: ld_out < output width");
+  if (!d_in || !d_out) return fail(MAXMIN_EINVAL, "maxmin_morph_2d: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_out, s))
+    return fail(MAXMIN_EINVAL, "maxmin_morph_2d: pointer not aligned to the element size");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* ws = nullptr;
+  int r = get_ws(st, &ws);
+  if (r) return r;
+  if ((r = ensure_tmp2(ws, (size_t)r1 * (size_t)c1 * s))) return r;
+  void* mid = ws->tmp2;
+  const bool open = op == MAXMIN_OPEN;  // opening: min first, then max
+  if ((r = maxmin_filter_2d(dtype, d_in, rows, cols, ld_in, w_rows, w_cols, open ? nullptr : mid, open ? mid : nullptr,
+                            c1, stream)))
+    return r;
+  return maxmin_filter_2d(dtype, mid, r1, c1, c1, w_rows, w_cols, open ? d_out : nullptr, open ? nullptr : d_out,
+                          ld_out, stream);
 }
 
 // Synchronise `stream` and report whether any look-back wait on it gave up.

@@ -116,8 +116,8 @@ __device__ __forceinline__ Series<T> job_series(const Job<T>& j, int64_t t, int6
     s.na = j.n;
     s.n = j.n;
     s.w = j.w;
-    s.omax = j.omax + k * j.ld_out;
-    s.omin = j.omin + k * j.ld_out;
+    s.omax = j.omax ? j.omax + k * j.ld_out : nullptr;  // a null output is not computed
+    s.omin = j.omin ? j.omin + k * j.ld_out : nullptr;
     s.carry = nullptr;
     return s;
   }
@@ -236,8 +236,9 @@ __device__ __forceinline__ void run_load(const Series<T>& s, const T* vb, int d,
   }
 }
 
-// Store the 8 outputs of positions q .. q+7 (only those < R1).  ovec: the
-// max and min outputs share the misalignment d (elements) at position q.
+// Store the 8 outputs of positions q .. q+7 (only those < R1).  om or on
+// may be null (that output is not wanted).  ovec: the outputs present share
+// the misalignment d (elements) at position q.
 template <class T>
 __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_t q, int64_t R1,
                                           const T (&ox)[kTileV], const T (&on_)[kTileV]) {
@@ -252,16 +253,16 @@ __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_
           u32x4 a, b;
           __builtin_memcpy(&a, &ox[k * EV], 16);
           __builtin_memcpy(&b, &on_[k * EV], 16);
-          gstore((u32x4*)(om + k * EV), a);
-          gstore((u32x4*)(on + k * EV), b);
+          if (om) gstore((u32x4*)(om + k * EV), a);
+          if (on) gstore((u32x4*)(on + k * EV), b);
         }
         break;
-#define MM_STORE_CASE(D)                \
-  case D:                               \
-    if constexpr (EV > D) {             \
-      store_shifted<T, D>(om, ox);      \
-      store_shifted<T, D>(on, on_);     \
-    }                                   \
+#define MM_STORE_CASE(D)                        \
+  case D:                                       \
+    if constexpr (EV > D) {                     \
+      if (om) store_shifted<T, D>(om, ox);      \
+      if (on) store_shifted<T, D>(on, on_);     \
+    }                                           \
     break;
       MM_STORE_CASE(1)
       MM_STORE_CASE(2)
@@ -276,8 +277,8 @@ __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_
 #pragma unroll
     for (int i = 0; i < V; ++i)
       if (q + i < R1) {
-        gstore(om + i, ox[i]);
-        gstore(on + i, on_[i]);
+        if (om) gstore(om + i, ox[i]);
+        if (on) gstore(on + i, on_[i]);
       }
   }
 }
@@ -307,9 +308,11 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   if (lim <= s.na) vbase = s.a;
   else if (R0 >= s.na) vbase = s.b - s.na;
   const int din = vbase != nullptr ? (int)(((uintptr_t)(vbase + R0) / sizeof(T)) & (EV - 1)) : 0;
-  const int dmx = (int)(((uintptr_t)(s.omax + R0) / sizeof(T)) & (EV - 1));
-  const int dmn = (int)(((uintptr_t)(s.omin + R0) / sizeof(T)) & (EV - 1));
-  const bool ovec = dmx == dmn;
+  // either output may be null (max-only / min-only filter)
+  const int dmx = s.omax ? (int)(((uintptr_t)(s.omax + R0) / sizeof(T)) & (EV - 1)) : -1;
+  const int dmn = s.omin ? (int)(((uintptr_t)(s.omin + R0) / sizeof(T)) & (EV - 1)) : -1;
+  const bool ovec = dmx < 0 || dmn < 0 || dmx == dmn;
+  const int dout = dmx >= 0 ? dmx : dmn;
   const bool last_run = R1 == nout;
 
   T cur[V], nxt[V];
@@ -424,11 +427,11 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
           lx[i] = R0 + ox[i].i;
           ln[i] = R0 + on[i].i;
         }
-        run_store<T>(s.omax + q0, s.omin + q0, ovec, dmx, q0, R1, vx, vn);
+        run_store<T>(s.omax ? s.omax + q0 : nullptr, s.omin ? s.omin + q0 : nullptr, ovec, dout, q0, R1, vx, vn);
         const int lmx = (int)(((uintptr_t)(amax + R0) / 8) & 1), lmn = (int)(((uintptr_t)(amin + R0) / 8) & 1);
         run_store<int64_t>(amax + q0, amin + q0, lmx == lmn, lmx, q0, R1, lx, ln);
       } else {
-        run_store<T>(s.omax + q0, s.omin + q0, ovec, dmx, q0, R1, ox, on);
+        run_store<T>(s.omax ? s.omax + q0 : nullptr, s.omin ? s.omin + q0 : nullptr, ovec, dout, q0, R1, ox, on);
       }
     }
 #pragma unroll
@@ -774,8 +777,8 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
     }
     __syncthreads();
     const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
-    chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
-    chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+    if (s.omax) chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+    if (s.omin) chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
   }
   __syncthreads();
 }
@@ -1022,8 +1025,8 @@ __device__ void crun_body(const Series<T>& s, int64_t c0, int64_t c1, CrunLds<T>
       }
       __syncthreads();
       const int rs = (int)max((int64_t)0, (w - 1) - p0);
-      chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
-      chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+      if (s.omax) chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+      if (s.omin) chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
@@ -1089,8 +1092,8 @@ __global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int
     d.na = n;
     d.n = n;
     d.w = w;
-    d.omax = d_max + out_off[k];
-    d.omin = d_min + out_off[k];
+    d.omax = d_max ? d_max + out_off[k] : nullptr;
+    d.omin = d_min ? d_min + out_off[k] : nullptr;
     d.carry = nullptr;
     descs[k] = d;
     pre_tile[k] = ra;

@@ -36,6 +36,8 @@ __global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* _
     Sx = reinterpret_cast<T*>(smem_raw);  // [w][64]
   T* Sn = Sx + 64 * w;
   const int lane = threadIdx.x;
+  // M (and omax) or N (and omin) is null for a min-only / max-only filter
+  const bool hx = M != nullptr, hn = N != nullptr;
   const int64_t c = (int64_t)blockIdx.x * 64 + lane;
   const bool act = c < oc;
   const int64_t cc = act ? c : 0;
@@ -51,9 +53,11 @@ __global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* _
 #pragma unroll
     for (int u = 0; u < kColBatch; ++u) {
       const int64_t i = i0 - u;
+      vx[u] = Lim<T>::lo();
+      vn[u] = Lim<T>::hi();
       if (i >= 0) {
-        vx[u] = M[(r0 + i) * ld_t + cc];
-        vn[u] = N[(r0 + i) * ld_t + cc];
+        if (hx) vx[u] = M[(r0 + i) * ld_t + cc];
+        if (hn) vn[u] = N[(r0 + i) * ld_t + cc];
       }
     }
 #pragma unroll
@@ -68,8 +72,8 @@ __global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* _
     }
   }
   if (act) {
-    omax[r0 * ld_out + c] = sx;  // window r0 is exactly the block
-    omin[r0 * ld_out + c] = sn;
+    if (hx) omax[r0 * ld_out + c] = sx;  // window r0 is exactly the block
+    if (hn) omin[r0 * ld_out + c] = sn;
   }
   // next block, top-down: prefix max/min over rows r0+w .. r0+w-1+i
   T px = Lim<T>::lo(), pn = Lim<T>::hi();
@@ -78,9 +82,11 @@ __global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* _
 #pragma unroll
     for (int u = 0; u < kColBatch; ++u) {
       const int64_t i = i0 + u;
+      vx[u] = Lim<T>::lo();
+      vn[u] = Lim<T>::hi();
       if (i < nb) {
-        vx[u] = M[(r0 + w - 1 + i) * ld_t + cc];
-        vn[u] = N[(r0 + w - 1 + i) * ld_t + cc];
+        if (hx) vx[u] = M[(r0 + w - 1 + i) * ld_t + cc];
+        if (hn) vn[u] = N[(r0 + w - 1 + i) * ld_t + cc];
       }
     }
 #pragma unroll
@@ -90,8 +96,8 @@ __global__ __launch_bounds__(64) void k_cols(const T* __restrict__ M, const T* _
         px = vmax(px, vx[u]);
         pn = vmin(pn, vn[u]);
         if (act) {
-          omax[(r0 + i) * ld_out + c] = vmax(Sx[i * 64 + lane], px);
-          omin[(r0 + i) * ld_out + c] = vmin(Sn[i * 64 + lane], pn);
+          if (hx) omax[(r0 + i) * ld_out + c] = vmax(Sx[i * 64 + lane], px);
+          if (hn) omin[(r0 + i) * ld_out + c] = vmin(Sn[i * 64 + lane], pn);
         }
       }
     }

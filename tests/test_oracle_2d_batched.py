@@ -10,6 +10,7 @@ import os
 
 import numpy as np
 import pytest
+from numpy.lib.stride_tricks import sliding_window_view
 
 import oracle
 from paper_cs_0610046_amd import synth
@@ -88,3 +89,48 @@ def test_synth_inputs_are_canonical():
     assert synth.check_canonical(x) and not np.signbit(x[0])
     r = synth.ramp_f32(100000)
     assert np.all(np.diff(r) > 0)
+
+
+def _morph_definition(a, op, wr, wc):
+    """Erosion / dilation straight from the rectangle definition, composed
+    for opening / closing (no wedge involved)."""
+    def er(x):
+        v = sliding_window_view(x, (wr, wc))
+        return v.min(axis=(2, 3))
+
+    def di(x):
+        v = sliding_window_view(x, (wr, wc))
+        return v.max(axis=(2, 3))
+    if op == "erode":
+        return er(a)
+    if op == "dilate":
+        return di(a)
+    return di(er(a)) if op == "open" else er(di(a))
+
+
+def test_morphology_equals_definition():
+    rng = np.random.default_rng(77)
+    for dt in (np.float32, np.float64, np.int32, np.uint16):
+        for (r, c, wr, wc) in ((9, 11, 3, 3), (12, 7, 2, 3), (20, 20, 5, 4), (6, 30, 1, 7), (8, 8, 4, 4)):
+            a = rng.integers(0, 6, (r, c)).astype(dt)
+            for op in ("erode", "dilate", "open", "close"):
+                got = oracle.morph2d(a, op, wr, wc)
+                want = _morph_definition(a, op, wr, wc)
+                assert got.shape == want.shape and np.array_equal(got, want), (dt, r, c, wr, wc, op)
+                assert np.array_equal(got, oracle.morph2d(a, op, wr, wc, filt=oracle.naive2d))
+
+
+def test_morphology_properties():
+    """Opening is anti-extensive and idempotent, closing extensive (on the
+    common valid region); erosion <= dilation."""
+    rng = np.random.default_rng(78)
+    a = rng.standard_normal((40, 50)).astype(np.float32)
+    w = 3
+    op = oracle.morph2d(a, "open", w)
+    cl = oracle.morph2d(a, "close", w)
+    inner = a[w - 1:a.shape[0] - w + 1, w - 1:a.shape[1] - w + 1]
+    assert np.all(op <= inner) and np.all(cl >= inner)
+    assert np.all(oracle.morph2d(a, "erode", w) <= oracle.morph2d(a, "dilate", w))
+    op2 = oracle.morph2d(op, "open", w)
+    # idempotence on the region both valid windows reach
+    assert np.array_equal(op2, op[w - 1:op.shape[0] - w + 1, w - 1:op.shape[1] - w + 1])
