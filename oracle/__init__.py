@@ -16,6 +16,9 @@ Comparisons per Element".
   opening and closing as compositions of the 2-D filter.
 * :func:`batched` / :func:`out_offsets` -- one filter per series of a packed
   buffer (independent series; the per-series call is the 1-D oracle).
+* :func:`envelope` / :func:`envelope_batched` -- centered envelopes (windows
+  [i-r, i+r] truncated at the ends; the time-warping lower-bound use the
+  paper cites in Section 1), from the definition.
 * :func:`argnaive` -- the leftmost location of each window's max and min,
   from the definition; :func:`argdeque` -- the same in linear time (the
   arg max/min filter the paper notes comes free with stored locations,
@@ -26,7 +29,9 @@ Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 invariants, hand-built worked examples and the paper's comparison bounds).
 """
 from .oracle import (DTYPES, build, load, naive, wedge, Stream, filter2d,
-                     naive2d, morph2d, batched, out_offsets, n_out, argnaive, argdeque)
+                     naive2d, morph2d, batched, out_offsets, n_out, argnaive, argdeque, envelope,
+                     envelope_batched)
 
 __all__ = ["DTYPES", "build", "load", "naive", "wedge", "Stream", "filter2d",
-           "naive2d", "morph2d", "batched", "out_offsets", "n_out", "argnaive", "argdeque"]
+           "naive2d", "morph2d", "batched", "out_offsets", "n_out", "argnaive", "argdeque", "envelope",
+           "envelope_batched"]

@@ -62,6 +62,8 @@ def load():
         for f in (lib.oracle_filter2d, lib.oracle_naive2d):
             f.argtypes = [ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _i64]
             f.restype = ctypes.c_int
+        lib.oracle_envelope.argtypes = [ctypes.c_int, _vp, _i64, _i64, _vp, _vp]
+        lib.oracle_envelope.restype = ctypes.c_int
         for f in (lib.oracle_argnaive, lib.oracle_argdeque):
             f.argtypes = [ctypes.c_int, _vp, _i64, _i64, _vp, _vp]
             f.restype = ctypes.c_int
@@ -130,6 +132,30 @@ def _arg(fn, a, w):
     if fn(_code(a), _ptr(a), a.size, int(w), _ptr(imx), _ptr(imn)) != 0:
         raise ValueError("bad arguments")
     return imx, imn
+
+
+def envelope(a, r):
+    """Centered envelope of radius r (definition): upper[i] / lower[i] = max /
+    min of a over [max(0, i-r), min(n-1, i+r)]."""
+    a = np.ascontiguousarray(a)
+    if int(r) < 0:
+        raise ValueError("r must be >= 0")
+    up = np.empty(a.size, a.dtype)
+    lo = np.empty(a.size, a.dtype)
+    if load().oracle_envelope(_code(a), _ptr(a), a.size, int(r), _ptr(up), _ptr(lo)) != 0:
+        raise ValueError("oracle_envelope: bad arguments")
+    return up, lo
+
+
+def envelope_batched(packed, in_offsets, radii):
+    """Envelope of each series of a packed buffer, packed the same way."""
+    packed = np.ascontiguousarray(packed)
+    up = np.empty_like(packed)
+    lo = np.empty_like(packed)
+    for k in range(len(radii)):
+        s, e = int(in_offsets[k]), int(in_offsets[k + 1])
+        up[s:e], lo[s:e] = envelope(packed[s:e], radii[k])
+    return up, lo
 
 
 def argnaive(a, w):

@@ -23,6 +23,8 @@
 //                  max (min).  The paper notes that an implementation that
 //                  stores locations gives this arg max/min filter at no
 //                  extra cost (Section 5); it fixes no rule for ties.
+//   * envelope     the centered envelope (windows [i-r, i+r] truncated at
+//                  the series ends), from the definition.
 //   * argdeque     the same locations from a monotonic deque of locations
 //                  that drops only strictly dominated entries (so equal
 //                  values stay and the front is the leftmost), pinned to
@@ -244,6 +246,24 @@ void argdeque(const T* a, int64_t n, int64_t w, int64_t* amx, int64_t* amn) {
   }
 }
 
+// Centered envelope of radius r: the max and min over
+// [max(0, i-r), min(n-1, i+r)] for every i (windows truncated at the series
+// ends), scanned directly.  The paper cites the use of a precomputed
+// max-min filter to bound the time warping distance (Section 1).
+template <class T>
+void envelope(const T* a, int64_t n, int64_t r, T* up, T* lo) {
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t j0 = i - r < 0 ? 0 : i - r, j1 = i + r > n - 1 ? n - 1 : i + r;
+    T M = a[j0], N = a[j0];
+    for (int64_t j = j0 + 1; j <= j1; ++j) {
+      if (a[j] > M) M = a[j];
+      if (a[j] < N) N = a[j];
+    }
+    up[i] = M;
+    lo[i] = N;
+  }
+}
+
 // dtype codes shared with the Python wrapper: 0 f32, 1 f64, 2 i32, 3 u16.
 struct StreamBox {
   int dt;
@@ -347,6 +367,12 @@ int oracle_argnaive(int dt, const void* a, int64_t n, int64_t w, int64_t* amx, i
 int oracle_argdeque(int dt, const void* a, int64_t n, int64_t w, int64_t* amx, int64_t* amn) {
   if (w < 1 || n < 0) return -1;
   ORACLE_DISPATCH(dt, argdeque<T>((const T*)a, n, w, amx, amn));
+  return 0;
+}
+
+int oracle_envelope(int dt, const void* a, int64_t n, int64_t r, void* up, void* lo) {
+  if (r < 0 || n < 0) return -1;
+  ORACLE_DISPATCH(dt, envelope<T>((const T*)a, n, r, (T*)up, (T*)lo));
   return 0;
 }
 

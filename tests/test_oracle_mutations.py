@@ -40,6 +40,10 @@ MUTATIONS = [
     ("deque drops equal values", "while (!U.empty() && a[U.back()] < x) U.pop_back();",
      "while (!U.empty() && a[U.back()] <= x) U.pop_back();"),
     ("deque expires one sample late", "if (L.front() <= i - w) L.pop_front();", "if (L.front() < i - w) L.pop_front();"),
+    ("envelope window one short at the right",
+     "j1 = i + r > n - 1 ? n - 1 : i + r;", "j1 = i + r > n - 1 ? n - 1 : i + r - (r > 0 ? 1 : 0);"),
+    ("envelope not truncated at the left", "const int64_t j0 = i - r < 0 ? 0 : i - r,",
+     "const int64_t j0 = i - r < 0 ? (r > 1 ? 1 : 0) : i - r,"),
 ]
 
 
@@ -57,6 +61,7 @@ def _compile(src_text, d):
     lib.oracle_filter2d.argtypes = [ctypes.c_int, vp, i64, i64, i64, i64, i64, vp, vp, i64]
     lib.oracle_argnaive.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp]
     lib.oracle_argdeque.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp]
+    lib.oracle_envelope.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp]
     return lib
 
 
@@ -110,6 +115,16 @@ def _pins_pass(lib):
             fn(1, a.ctypes.data, a.size, w, imx.ctypes.data, imn.ctypes.data)
             if not (np.array_equal(imx, v.argmax(1) + j) and np.array_equal(imn, v.argmin(1) + j)):
                 return False
+    from scipy.ndimage import maximum_filter1d, minimum_filter1d
+    for it in range(100):
+        n = int(rng.integers(1, 60))
+        r = int(rng.integers(0, n + 2))
+        a = rng.integers(0, 9, n).astype(np.float64)
+        up, lo = np.zeros(n), np.zeros(n)
+        lib.oracle_envelope(1, a.ctypes.data, n, r, up.ctypes.data, lo.ctypes.data)
+        if not (np.array_equal(up, maximum_filter1d(a, 2 * r + 1, mode="nearest")) and
+                np.array_equal(lo, minimum_filter1d(a, 2 * r + 1, mode="nearest"))):
+            return False
     for ex in GOLD["two_d"]:
         a = np.array(ex["a"], np.float64)
         r, c = a.shape
