@@ -158,6 +158,32 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
                      int64_t w_rows, int64_t w_cols, void* d_max, void* d_min, int64_t ld_out,
                      void* stream);
 
+/*
+ * maxmin_envelope -- centered envelope of radius r >= 0 (the precomputed
+ * max-min filter used to bound the time warping distance, Section 1):
+ *   d_upper[i] = max of d_in over [max(0, i-r), min(n-1, i+r)], d_lower
+ *   likewise; n outputs each (windows truncated at the series ends).
+ * The interior runs the 1-D filter with w = 2r+1; the two ends are scans.
+ * Errors: EINVAL if r < 0, n < 0, or a pointer is null / misaligned while
+ * n > 0.
+ */
+int maxmin_envelope(int dtype, const void* d_in, int64_t n, int64_t r, void* d_upper, void* d_lower,
+                    void* stream);
+
+/*
+ * maxmin_envelope_batched -- the envelope of each of S packed series, with
+ * per-series radii: series k is d_in[d_in_offsets[k] .. d_in_offsets[k+1])
+ * with radius d_radii[k] >= 0, and its envelope goes to the same positions
+ * of d_upper / d_lower.  d_in_offsets [S+1] and d_radii [S] are DEVICE int64
+ * arrays, not validated on the host (a negative radius leaves that series'
+ * outputs unwritten).  Uses library scratch of (2S+1) int64 and the batched
+ * filter (graph replay on repeat).
+ * Errors: EINVAL if S < 0 or a pointer is null while S > 0.
+ */
+int maxmin_envelope_batched(int dtype, const void* d_in, const int64_t* d_in_offsets,
+                            const int64_t* d_radii, int64_t S, void* d_upper, void* d_lower,
+                            void* stream);
+
 /* Grey-scale morphology operators of maxmin_morph_2d. */
 typedef enum {
   MAXMIN_ERODE = 0,  /* min over the rectangle (the min half of maxmin_filter_2d) */

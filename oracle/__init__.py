@@ -16,6 +16,9 @@ Comparisons per Element".
   opening and closing as compositions of the 2-D filter.
 * :func:`batched` / :func:`out_offsets` -- one filter per series of a packed
   buffer (independent series; the per-series call is the 1-D oracle).
+* :func:`vhgw`, :func:`gil_kimmel`, :func:`minmax3` -- other exact filters
+  the paper reviews (Related Work; the w = 3 proposition), with comparison
+  counts: cross-checks of the definition and of the paper's bounds.
 * :func:`envelope` / :func:`envelope_batched` -- centered envelopes (windows
   [i-r, i+r] truncated at the ends; the time-warping lower-bound use the
   paper cites in Section 1), from the definition.
@@ -30,8 +33,8 @@ invariants, hand-built worked examples and the paper's comparison bounds).
 """
 from .oracle import (DTYPES, build, load, naive, wedge, Stream, filter2d,
                      naive2d, morph2d, batched, out_offsets, n_out, argnaive, argdeque, envelope,
-                     envelope_batched)
+                     envelope_batched, vhgw, gil_kimmel, minmax3)
 
 __all__ = ["DTYPES", "build", "load", "naive", "wedge", "Stream", "filter2d",
            "naive2d", "morph2d", "batched", "out_offsets", "n_out", "argnaive", "argdeque", "envelope",
-           "envelope_batched"]
+           "envelope_batched", "vhgw", "gil_kimmel", "minmax3"]

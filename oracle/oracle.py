@@ -62,6 +62,11 @@ def load():
         for f in (lib.oracle_filter2d, lib.oracle_naive2d):
             f.argtypes = [ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _i64]
             f.restype = ctypes.c_int
+        for f in (lib.oracle_vhgw, lib.oracle_gil_kimmel):
+            f.argtypes = [ctypes.c_int, _vp, _i64, _i64, _vp, _vp]
+            f.restype = _i64
+        lib.oracle_minmax3.argtypes = [ctypes.c_int, _vp, _i64, _vp, _vp]
+        lib.oracle_minmax3.restype = _i64
         lib.oracle_envelope.argtypes = [ctypes.c_int, _vp, _i64, _i64, _vp, _vp]
         lib.oracle_envelope.restype = ctypes.c_int
         for f in (lib.oracle_argnaive, lib.oracle_argdeque):
@@ -132,6 +137,33 @@ def _arg(fn, a, w):
     if fn(_code(a), _ptr(a), a.size, int(w), _ptr(imx), _ptr(imn)) != 0:
         raise ValueError("bad arguments")
     return imx, imn
+
+
+def _cross(fn, a, w):
+    a = np.ascontiguousarray(a)
+    k = n_out(a.size, w)
+    mx = np.empty(k, a.dtype)
+    mn = np.empty(k, a.dtype)
+    c = fn(a, mx, mn)
+    if c < 0:
+        raise ValueError("bad arguments")
+    return mx, mn, int(c)
+
+
+def vhgw(a, w):
+    """van Herk / Gil-Werman (Related Work): ``(max, min, comparisons)``."""
+    return _cross(lambda a, x, y: load().oracle_vhgw(_code(a), _ptr(a), a.size, int(w), _ptr(x), _ptr(y)), a, w)
+
+
+def gil_kimmel(a, w):
+    """Gil-Kimmel (Related Work): ``(max, min, comparisons)``."""
+    return _cross(lambda a, x, y: load().oracle_gil_kimmel(_code(a), _ptr(a), a.size, int(w), _ptr(x), _ptr(y)), a, w)
+
+
+def minmax3(a):
+    """The two-comparison w = 3 filter (lower-bound section):
+    ``(max, min, comparisons)``."""
+    return _cross(lambda a, x, y: load().oracle_minmax3(_code(a), _ptr(a), a.size, _ptr(x), _ptr(y)), a, 3)
 
 
 def envelope(a, r):

@@ -23,6 +23,9 @@
 //                  max (min).  The paper notes that an implementation that
 //                  stores locations gives this arg max/min filter at no
 //                  extra cost (Section 5); it fixes no rule for ties.
+//   * vhgw1, gk1, minmax3  other exact filters the paper reviews (van Herk /
+//                  Gil-Werman, Gil-Kimmel, and the two-comparison w = 3
+//                  algorithm), as cross-checks with comparison counts.
 //   * envelope     the centered envelope (windows [i-r, i+r] truncated at
 //                  the series ends), from the definition.
 //   * argdeque     the same locations from a monotonic deque of locations
@@ -264,6 +267,116 @@ void envelope(const T* a, int64_t n, int64_t r, T* up, T* lo) {
   }
 }
 
+// ------------------------------------------------ cross-check algorithms
+// Other exact max-min filters the paper reviews (Related Work, and the
+// proposition on w = 3 in the lower-bound section), written from their
+// descriptions, with value comparisons counted.  They give the same outputs
+// as the definition by a different route and check the paper's comparison
+// bounds for them.
+
+// One direction of a filter: better(x, y) is x > y (max) or x < y (min).
+template <class T, bool MAX>
+struct Better {
+  int64_t* n;
+  bool operator()(T x, T y) const {
+    ++*n;
+    return MAX ? x > y : x < y;
+  }
+};
+// the better of x and y, x on ties
+template <class T, class C> T pick(T x, T y, C& c) { return c(y, x) ? y : x; }
+
+// van Herk / Gil-Werman: blocks of w; prefix extrema over each block
+// (w-1 comparisons), suffix extrema over all but its first position (w-2);
+// the window starting at a block start is that block (its last prefix), any
+// other window is the suffix of its first block against the prefix of the
+// next (1 comparison): 3w-4 per block and direction.
+template <class T, bool MAX>
+void vhgw1(const T* a, int64_t n, int64_t w, T* out, int64_t* cnt) {
+  Better<T, MAX> c{cnt};
+  std::vector<T> P((size_t)n), S((size_t)n);
+  for (int64_t b0 = 0; b0 < n; b0 += w) {
+    const int64_t b1 = b0 + w < n ? b0 + w : n;
+    P[(size_t)b0] = a[b0];
+    for (int64_t i = b0 + 1; i < b1; ++i) P[(size_t)i] = pick(P[(size_t)(i - 1)], a[i], c);
+    S[(size_t)(b1 - 1)] = a[b1 - 1];
+    for (int64_t i = b1 - 2; i > b0; --i) S[(size_t)i] = pick(S[(size_t)(i + 1)], a[i], c);
+  }
+  for (int64_t j = 0; j + w <= n; ++j)
+    out[j] = j % w == 0 ? P[(size_t)(j + w - 1)] : pick(S[(size_t)j], P[(size_t)(j + w - 1)], c);
+}
+
+// Gil-Kimmel, both improvements: (1) a block's prefix extrema stop changing
+// after its best element and its suffix extrema before it, so compute the
+// prefix over the first half and the suffix over the second, compare their
+// ends once to learn which half holds the best, and compute only the other
+// two halves that can still change; (2) across the windows starting in a
+// block, the suffix term only worsens and the prefix term only improves, so
+// a binary search finds where the prefix takes over.
+template <class T, bool MAX>
+void gk1(const T* a, int64_t n, int64_t w, T* out, int64_t* cnt) {
+  Better<T, MAX> c{cnt};
+  std::vector<T> P((size_t)n), S((size_t)n);
+  for (int64_t b0 = 0; b0 < n; b0 += w) {
+    const int64_t b1 = b0 + w < n ? b0 + w : n, len = b1 - b0, q = (len + 1) / 2;
+    P[(size_t)b0] = a[b0];
+    for (int64_t i = b0 + 1; i < b0 + q; ++i) P[(size_t)i] = pick(P[(size_t)(i - 1)], a[i], c);
+    S[(size_t)(b1 - 1)] = a[b1 - 1];
+    for (int64_t i = b1 - 2; i >= b0 + q; --i) S[(size_t)i] = pick(S[(size_t)(i + 1)], a[i], c);
+    if (q == len) continue;  // a one-element block
+    const bool first = !c(S[(size_t)(b0 + q)], P[(size_t)(b0 + q - 1)]);  // ties: the first half
+    if (first) {
+      for (int64_t i = b0 + q; i < b1; ++i) P[(size_t)i] = P[(size_t)(b0 + q - 1)];
+      for (int64_t i = b0 + q - 1; i > b0; --i) S[(size_t)i] = pick(S[(size_t)(i + 1)], a[i], c);
+    } else {
+      for (int64_t i = b0 + q; i < b1; ++i) P[(size_t)i] = pick(P[(size_t)(i - 1)], a[i], c);
+      for (int64_t i = b0 + q - 1; i > b0; --i) S[(size_t)i] = S[(size_t)(b0 + q)];
+    }
+  }
+  for (int64_t b0 = 0; b0 + w <= n; b0 += w) {
+    out[b0] = P[(size_t)(b0 + w - 1)];  // the window is the block
+    // windows j in (b0, e): the first j whose prefix term is at least as good
+    const int64_t e = b0 + w < n - w + 1 ? b0 + w : n - w + 1;
+    int64_t lo = b0 + 1, hi = e;  // answer in [lo, hi]; hi = e: never
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (!c(S[(size_t)mid], P[(size_t)(mid + w - 1)])) hi = mid;
+      else lo = mid + 1;
+    }
+    for (int64_t j = b0 + 1; j < e; ++j) out[j] = j < lo ? S[(size_t)j] : P[(size_t)(j + w - 1)];
+  }
+}
+
+template <class T>
+void vhgw(const T* a, int64_t n, int64_t w, T* mx, T* mn, int64_t* cnt) {
+  vhgw1<T, true>(a, n, w, mx, cnt);
+  vhgw1<T, false>(a, n, w, mn, cnt);
+}
+
+template <class T>
+void gil_kimmel(const T* a, int64_t n, int64_t w, T* mx, T* mn, int64_t* cnt) {
+  gk1<T, true>(a, n, w, mx, cnt);
+  gk1<T, false>(a, n, w, mn, cnt);
+}
+
+// w = 3 with two comparisons per element (the paper's proposition): the
+// order of the last two samples is known from the previous step, so
+// comparing the new sample with each of them orders all three.
+template <class T>
+void minmax3(const T* a, int64_t n, T* mx, T* mn, int64_t* cnt) {
+  if (n < 3) return;
+  ++*cnt;
+  bool up = a[1] > a[0];  // a[i-1] > a[i-2]
+  for (int64_t i = 2; i < n; ++i) {
+    const bool c1 = a[i] > a[i - 1], c2 = a[i] > a[i - 2];
+    *cnt += 2;
+    const T hi2 = up ? a[i - 1] : a[i - 2], lo2 = up ? a[i - 2] : a[i - 1];
+    mx[i - 2] = (up ? c1 : c2) ? a[i] : hi2;  // a[i] beats the larger of the two
+    mn[i - 2] = (up ? c2 : c1) ? lo2 : a[i];  // a[i] above the smaller: that one
+    up = c1;
+  }
+}
+
 // dtype codes shared with the Python wrapper: 0 f32, 1 f64, 2 i32, 3 u16.
 struct StreamBox {
   int dt;
@@ -374,6 +487,27 @@ int oracle_envelope(int dt, const void* a, int64_t n, int64_t r, void* up, void*
   if (r < 0 || n < 0) return -1;
   ORACLE_DISPATCH(dt, envelope<T>((const T*)a, n, r, (T*)up, (T*)lo));
   return 0;
+}
+
+int64_t oracle_vhgw(int dt, const void* a, int64_t n, int64_t w, void* mx, void* mn) {
+  if (w < 1 || n < 0) return -1;
+  int64_t k = 0;
+  ORACLE_DISPATCH(dt, vhgw<T>((const T*)a, n, w, (T*)mx, (T*)mn, &k));
+  return k;
+}
+
+int64_t oracle_gil_kimmel(int dt, const void* a, int64_t n, int64_t w, void* mx, void* mn) {
+  if (w < 1 || n < 0) return -1;
+  int64_t k = 0;
+  ORACLE_DISPATCH(dt, gil_kimmel<T>((const T*)a, n, w, (T*)mx, (T*)mn, &k));
+  return k;
+}
+
+int64_t oracle_minmax3(int dt, const void* a, int64_t n, void* mx, void* mn) {
+  if (n < 0) return -1;
+  int64_t k = 0;
+  ORACLE_DISPATCH(dt, minmax3<T>((const T*)a, n, (T*)mx, (T*)mn, &k));
+  return k;
 }
 
 }  // extern "C"

@@ -51,6 +51,8 @@ def lib():
         L.maxmin_stream_samples.restype = i64
         L.maxmin_filter_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, vp, vp, i64, vp]
         L.maxmin_morph_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, ci, vp, i64, vp]
+        L.maxmin_envelope.argtypes = [ci, vp, i64, i64, vp, vp, vp]
+        L.maxmin_envelope_batched.argtypes = [ci, vp, vp, vp, i64, vp, vp, vp]
         L.maxmin_set_strategy.argtypes = [ci]
         L.maxmin_plan.argtypes = [ci, i64, i64]
         L.maxmin_check_stream.argtypes = [vp]
@@ -75,6 +77,7 @@ def lib():
         L.maxmin_version.restype = ctypes.c_char_p
         for f in ("maxmin_filter", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
                   "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_morph_2d",
+                  "maxmin_envelope", "maxmin_envelope_batched",
                   "maxmin_set_strategy",
                   "maxmin_plan", "maxmin_check_stream"):
             getattr(L, f).restype = ci
@@ -270,6 +273,30 @@ def maxmin_filter_2d(img, w_rows, w_cols=None, out_max=None, out_min=None, strea
     _check(lib().maxmin_filter_2d(dtype_code(img.dtype), _ptr(img), rows, cols, img.stride(0) if rows else cols,
                                   int(w_rows), int(w_cols), _ptr(out_max), _ptr(out_min), ld_out, _stream(stream)))
     return out_max, out_min
+
+
+def maxmin_envelope(x, r, out_upper=None, out_lower=None, stream=None):
+    """Centered envelope of radius r: max / min over [i-r, i+r] truncated at
+    the ends (n outputs each).  Returns (upper, lower)."""
+    import torch
+    _cuda_1d(x, "x")
+    out_upper = torch.empty_like(x) if out_upper is None else out_upper
+    out_lower = torch.empty_like(x) if out_lower is None else out_lower
+    _check(lib().maxmin_envelope(dtype_code(x.dtype), _ptr(x), x.numel(), int(r), _ptr(out_upper), _ptr(out_lower),
+                                 _stream(stream)))
+    return out_upper, out_lower
+
+
+def maxmin_envelope_batched(packed, in_offsets, radii, out_upper=None, out_lower=None, stream=None):
+    """Envelopes of S packed series (device int64 ``in_offsets`` [S+1] and
+    ``radii`` [S]), packed like the input."""
+    import torch
+    _cuda_1d(packed, "packed")
+    out_upper = torch.empty_like(packed) if out_upper is None else out_upper
+    out_lower = torch.empty_like(packed) if out_lower is None else out_lower
+    _check(lib().maxmin_envelope_batched(dtype_code(packed.dtype), _ptr(packed), _ptr(in_offsets), _ptr(radii),
+                                         radii.numel(), _ptr(out_upper), _ptr(out_lower), _stream(stream)))
+    return out_upper, out_lower
 
 
 MORPH_OPS = {"erode": 0, "dilate": 1, "open": 2, "close": 3}

@@ -110,6 +110,8 @@ struct Workspace {
   size_t tmp_bytes = 0;
   void* tmp2 = nullptr;  // morphology: the first filter's image
   size_t tmp2_bytes = 0;
+  void* env = nullptr;  // batched envelopes: windows [S] and output offsets [S+1]
+  size_t env_bytes = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -622,6 +624,61 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (rows)");
   e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (columns)");
+  return ok();
+}
+
+// Centered envelope: the interior is the valid filter of width 2r+1 written
+// at offset r; the two truncated ends come from k_env_ends.
+int maxmin_envelope(int dtype, const void* d_in, int64_t n, int64_t r, void* d_upper, void* d_lower, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_envelope: unknown dtype %d", dtype);
+  if (r < 0) return fail(MAXMIN_EINVAL, "maxmin_envelope: radius r=%lld < 0", (long long)r);
+  if (n < 0) return fail(MAXMIN_EINVAL, "maxmin_envelope: n=%lld < 0", (long long)n);
+  if (n == 0) return ok();
+  if (!d_in || !d_upper || !d_lower) return fail(MAXMIN_EINVAL, "maxmin_envelope: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_upper, s) || !aligned(d_lower, s))
+    return fail(MAXMIN_EINVAL, "maxmin_envelope: pointer not aligned to the element size");
+  if (r > (n - 1) / 2 + n) r = (n - 1) / 2 + n;  // larger radii change nothing (and 2r+1 cannot overflow)
+  hipStream_t st = (hipStream_t)stream;
+  if (n >= 2 * r + 1) {
+    JobArgs a;
+    a.mode = 0;
+    a.a = d_in;
+    a.na = n;
+    a.n = n;
+    a.w = 2 * r + 1;
+    a.omax = (char*)d_upper + (size_t)r * s;
+    a.omin = (char*)d_lower + (size_t)r * s;
+    const int rr = run_series(dtype, a, st, "maxmin_envelope (interior)");
+    if (rr) return rr;
+  }
+  hipError_t e = mm::launch_env_ends(dtype, d_in, n, r, d_upper, d_lower, st);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_envelope (ends)");
+  return ok();
+}
+
+int maxmin_envelope_batched(int dtype, const void* d_in, const int64_t* d_in_offsets, const int64_t* d_radii, int64_t S,
+                            void* d_upper, void* d_lower, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_envelope_batched: unknown dtype %d", dtype);
+  if (S < 0) return fail(MAXMIN_EINVAL, "maxmin_envelope_batched: S < 0");
+  if (S == 0) return ok();
+  if (!d_in || !d_in_offsets || !d_radii || !d_upper || !d_lower)
+    return fail(MAXMIN_EINVAL, "maxmin_envelope_batched: null pointer");
+  if (!aligned(d_in, s) || !aligned(d_upper, s) || !aligned(d_lower, s))
+    return fail(MAXMIN_EINVAL, "maxmin_envelope_batched: pointer not aligned to the element size");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* ws = nullptr;
+  int r = get_ws(st, &ws);
+  if (r) return r;
+  if ((r = ensure_buf(ws, &ws->env, &ws->env_bytes, (size_t)(2 * S + 1) * sizeof(int64_t)))) return r;
+  int64_t* wins = (int64_t*)ws->env;
+  int64_t* oo = wins + S;
+  hipError_t e = mm::launch_env_batched(dtype, d_in, d_in_offsets, d_radii, S, wins, oo, true, nullptr, nullptr, st);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_envelope_batched (setup)");
+  if ((r = maxmin_filter_batched(dtype, d_in, d_in_offsets, wins, oo, S, d_upper, d_lower, stream))) return r;
+  e = mm::launch_env_batched(dtype, d_in, d_in_offsets, d_radii, S, nullptr, nullptr, false, d_upper, d_lower, st);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_envelope_batched (ends)");
   return ok();
 }
 

@@ -853,6 +853,117 @@ __global__ __launch_bounds__(256) void k_argcombine(const T* __restrict__ vx, co
   }
 }
 
+// ==================================================== centered envelopes
+// Envelope of radius r: upper[i] / lower[i] = max / min over
+// [max(0, i-r), min(n-1, i+r)] (windows truncated at the series ends; the
+// time-warping lower bound the paper cites in Section 1).  The interior
+// i in [r, n-1-r] is the valid filter of width 2r+1, written by the 1-D
+// kernels at offset r; these kernels write the two truncated ends.  One
+// workgroup scans an end (the first or the last min(n, 2r) elements) in
+// tiles of 2048 with a running carry: scan index k (position k from the
+// left, or n-1-k from the right) gives the output at k-r (left) or
+// n-1-k+r (right) once k >= r.  When n <= 2r the left scan reaches the last
+// element and its total is the envelope of every window truncated at both
+// ends.
+template <class T>
+__device__ void env_end(const T* a, int64_t n, int64_t r, T* up, T* lo, bool left, T* sx, T* sn) {
+  constexpr int V = 8, NT = 256, TT = NT * V;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m = min(n, 2 * r);
+  T cx = Lim<T>::lo(), cn = Lim<T>::hi();  // over the tiles already scanned
+  for (int64_t base = 0; base < m; base += TT) {
+    T px[V], pn[V];
+    T rx = Lim<T>::lo(), rn = Lim<T>::hi();
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int64_t k = base + tid * V + i;
+      if (k < m) {
+        const T v = gload(a + (left ? k : n - 1 - k));
+        rx = vmax(rx, v);
+        rn = vmin(rn, v);
+      }
+      px[i] = rx;
+      pn[i] = rn;
+    }
+    // exclusive prefix of the thread totals: lanes, then waves
+    T ix = rx, in = rn;
+    wave_prefix2(ix, in);
+    T ex = shup(ix, 1, 64), en = shup(in, 1, 64);
+    if (lane == 0) {
+      ex = Lim<T>::lo();
+      en = Lim<T>::hi();
+    }
+    if (lane == 63) {
+      sx[wv] = ix;
+      sn[wv] = in;
+    }
+    __syncthreads();
+    T wx = Lim<T>::lo(), wn = Lim<T>::hi(), tx = Lim<T>::lo(), tn = Lim<T>::hi();
+#pragma unroll
+    for (int v = 0; v < NT / 64; ++v) {
+      if (v < wv) {
+        wx = vmax(wx, sx[v]);
+        wn = vmin(wn, sn[v]);
+      }
+      tx = vmax(tx, sx[v]);
+      tn = vmin(tn, sn[v]);
+    }
+    __syncthreads();  // sx / sn are rewritten by the next tile
+    const T ox = vmax(cx, vmax(wx, ex)), on = vmin(cn, vmin(wn, en));
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int64_t k = base + tid * V + i;
+      if (k < m && k >= r) {
+        const int64_t o = left ? k - r : n - 1 - k + r;
+        gstore(up + o, vmax(ox, px[i]));
+        gstore(lo + o, vmin(on, pn[i]));
+      }
+    }
+    cx = vmax(cx, tx);
+    cn = vmin(cn, tn);
+  }
+  if (left && m == n) {
+    // windows truncated at both ends: the whole series
+    for (int64_t i = max((int64_t)0, n - r) + tid; i < min(r, n); i += NT) {
+      gstore(up + i, cx);
+      gstore(lo + i, cn);
+    }
+  }
+}
+
+// blockIdx.x: 0 the left end, 1 the right end
+template <class T>
+__global__ __launch_bounds__(256) void k_env_ends(const T* a, int64_t n, int64_t r, T* up, T* lo) {
+  __shared__ T sx[4], sn[4];
+  env_end<T>(a, n, r, up, lo, blockIdx.x == 0, sx, sn);
+}
+
+// series k = blockIdx.x + j * gridDim.x; blockIdx.y: 0 left end, 1 right end
+template <class T>
+__global__ __launch_bounds__(256) void k_env_ends_batched(const T* in, const int64_t* off, const int64_t* radii,
+                                                          int64_t S, T* up, T* lo) {
+  __shared__ T sx[4], sn[4];
+  for (int64_t k = blockIdx.x; k < S; k += gridDim.x) {
+    const int64_t s0 = off[k], n = off[k + 1] - s0, r = radii[k];
+    if (r > 0 && n > 0) env_end<T>(in + s0, n, r, up + s0, lo + s0, blockIdx.y == 0, sx, sn);
+  }
+}
+
+// Batched envelope interiors as a batched filter: window 2r+1, outputs at
+// the series' own offset + r.  A negative radius gives a window < 1, which
+// the batched filter skips.
+__global__ __launch_bounds__(256) void k_env_setup(const int64_t* off, const int64_t* radii, int64_t S, int64_t* wins,
+                                                    int64_t* oo) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= S; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < S) {
+      wins[k] = 2 * radii[k] + 1;
+      oo[k] = off[k] + radii[k];
+    } else {
+      oo[k] = off[k];
+    }
+  }
+}
+
 // ============================================ chunk runs (local aggregates)
 // Same window-aligned chunks as above (at most kCrMax inputs), but a
 // workgroup walks a run of consecutive chunks of one series and keeps the
@@ -1249,6 +1360,32 @@ hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const i
     using T = std::remove_pointer_t<decltype(p)>;
     hipLaunchKernelGGL(k_argcombine<T>, dim3(grid), dim3(256), 0, st, (const T*)vx, (const T*)vn, ix, in_, d, nout,
                        (T*)ox, (T*)on, jx, jn);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_env_ends(int dtype, const void* a, int64_t n, int64_t r, void* up, void* lo, hipStream_t st) {
+  if (n <= 0 || r <= 0) return hipSuccess;
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    hipLaunchKernelGGL(k_env_ends<T>, dim3(2), dim3(256), 0, st, (const T*)a, n, r, (T*)up, (T*)lo);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_env_batched(int dtype, const void* in, const int64_t* off, const int64_t* radii, int64_t S,
+                              int64_t* wins, int64_t* oo, bool setup, void* up, void* lo, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  if (setup) {
+    const int g = (int)std::min<int64_t>((S + 256) / 256, 1024);
+    hipLaunchKernelGGL(k_env_setup, dim3(g), dim3(256), 0, st, off, radii, S, wins, oo);
+    return hipGetLastError();
+  }
+  const int g = (int)std::min<int64_t>(S, 65535);
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    hipLaunchKernelGGL(k_env_ends_batched<T>, dim3(g, 2), dim3(256), 0, st, (const T*)in, off, radii, S, (T*)up,
+                       (T*)lo);
     return hipGetLastError();
   });
 }

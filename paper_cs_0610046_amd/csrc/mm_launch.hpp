@@ -113,6 +113,12 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
 // A stream push that completes no window: new carry = last min(n, w-1)
 // samples of (a[0..na) ++ b).
 hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st);
+// Centered envelopes: the two truncated ends of one series; for a batch,
+// either the setup of the interiors' window / output-offset arrays (setup)
+// or the ends of every series.
+hipError_t launch_env_ends(int dtype, const void* a, int64_t n, int64_t r, void* up, void* lo, hipStream_t st);
+hipError_t launch_env_batched(int dtype, const void* in, const int64_t* off, const int64_t* radii, int64_t S,
+                              int64_t* wins, int64_t* oo, bool setup, void* up, void* lo, hipStream_t st);
 // One doubling step of the arg filter (see k_argcombine): outputs j < nout
 // from inputs j and j + d of the shorter window's value/location arrays.
 hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,
