@@ -17,6 +17,9 @@ Also reported on the same JSON line (not part of ``value``):
   [1e3, 1e6], windows uniform in [2, 1024], one batched call (graph replay),
 * ``image``        -- 8192 x 8192 float32, w x w windows, rows then columns,
 * ``argfilter``    -- n = 2**28 float32 walk, values plus leftmost locations,
+* ``max_only``     -- the same walk, w = 256, only the max output,
+* ``envelope``     -- centered envelopes of 100,000 walks of 1024 samples,
+* ``morphology``   -- opening of the 8192 x 8192 field with a 15 x 15 square,
 * ``cpu_baseline`` -- the CPU oracle (single thread) on a bounded sample.
 """
 import argparse
@@ -291,6 +294,51 @@ def run_extras(torch, mm, synth, dev, stream):
                                     "(algorithmic bytes: 4 read + 24 written per window)", "per_window": res}
     print("[bench] argfilter done", file=sys.stderr, flush=True)
     del xa
+
+    # max-only filter: n = 2^28 float32 walk, w = 256, min output not requested
+    xm = torch.from_numpy(synth.random_walk(1 << 28, np.float32, synth.rng_for("large", 0))).to(dev)
+    om = torch.empty(xm.numel() - 255, device=dev)
+    mm.maxmin_filter(xm, 256, om, None, which="max")
+    ts = timed(lambda: mm.maxmin_filter(xm, 256, om, None, which="max"), 5, stream)
+    ms = float(np.median(ts))
+    ab = xm.numel() * 4 + om.numel() * 4
+    out["max_only"] = {"workload": "n=2^28 float32 walk, w=256, max output only (4 read + 4 written per window)",
+                       "ms": round(ms, 4), "gelem_s": round(xm.numel() / (ms * 1e-3) / 1e9, 2),
+                       "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+    del xm, om
+
+    # centered envelopes over a batch of candidates (time-warping bounds)
+    S, L = 100000, 1024
+    rng = synth.rng_for("envelope", 0)
+    radii = rng.integers(10, 101, S).astype(np.int64)
+    offs = np.arange(S + 1, dtype=np.int64) * L
+    xe = torch.from_numpy(synth.random_walk(S * L, np.float32, rng)).to(dev)
+    d_off, d_r = torch.from_numpy(offs).to(dev), torch.from_numpy(radii).to(dev)
+    eu, el = torch.empty_like(xe), torch.empty_like(xe)
+    for _ in range(2):
+        mm.maxmin_envelope_batched(xe, d_off, d_r, eu, el)
+    ts = timed(lambda: mm.maxmin_envelope_batched(xe, d_off, d_r, eu, el), 5, stream)
+    ms = float(np.median(ts))
+    ab = 3 * xe.numel() * 4
+    out["envelope"] = {"workload": "100,000 float32 walks of 1024 samples, radius uniform [10, 100], one batched "
+                                   "call (interiors by graph replay + end scans)",
+                       "ms": round(ms, 4), "gelem_s": round(xe.numel() / (ms * 1e-3) / 1e9, 2),
+                       "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+    del xe, eu, el
+
+    # morphology: opening of the 8192^2 float32 field with a 15 x 15 square
+    img = synth.gaussian_field(8192, 8192)
+    xi = torch.from_numpy(img).to(dev)
+    del img
+    oo = mm.maxmin_morph_2d(xi, "open", 15)
+    ts = timed(lambda: mm.maxmin_morph_2d(xi, "open", 15, out=oo), 5, stream)
+    ms = float(np.median(ts))
+    ab = xi.numel() * 4 + oo.numel() * 4
+    out["morphology"] = {"workload": "opening of the 8192x8192 float32 field, 15x15 square (erosion then dilation, "
+                                     "each rows then columns)", "ms": round(ms, 4),
+                         "gelem_s": round(xi.numel() / (ms * 1e-3) / 1e9, 2),
+                         "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+    del xi, oo
 
     # serving: Poisson filter requests + 1000 persistent streams, 64 GB budget
     from paper_cs_0610046_amd.serving import serving_run

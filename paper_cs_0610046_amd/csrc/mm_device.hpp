@@ -29,6 +29,28 @@ template <> struct Lim<uint16_t> {
 // Selection only: compare, then pick one operand's bits unchanged.
 template <class T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
 template <class T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
+// hmax / hmin: the same selection through the hardware max/min for floating
+// types (v_max_f32 / v_max_f64; the compiler adds one canonicalising max per
+// loaded value).  For the inputs the library accepts -- no NaN, no -0.0 --
+// they return one operand's bits unchanged, exactly as the compare-select:
+// the larger (smaller) value, and equal values have equal bits; denormals
+// are kept (no flush mode is set).  On MI355X this sped up the chunk kernel
+// by 3-4% and slowed the tile kernel, whose lane scans then re-canonicalise
+// every shuffled value; only the chunk kernel uses them.
+template <class T> __device__ __forceinline__ T hmax(T a, T b) { return vmax(a, b); }
+template <class T> __device__ __forceinline__ T hmin(T a, T b) { return vmin(a, b); }
+template <> __device__ __forceinline__ float hmax<float>(float a, float b) { return __builtin_fmaxf(a, b); }
+template <> __device__ __forceinline__ float hmin<float>(float a, float b) { return __builtin_fminf(a, b); }
+template <> __device__ __forceinline__ double hmax<double>(double a, double b) { return __builtin_fmax(a, b); }
+template <> __device__ __forceinline__ double hmin<double>(double a, double b) { return __builtin_fmin(a, b); }
+template <bool HW, class T> __device__ __forceinline__ T smax(T a, T b) {
+  if constexpr (HW) return hmax(a, b);
+  else return vmax(a, b);
+}
+template <bool HW, class T> __device__ __forceinline__ T smin(T a, T b) {
+  if constexpr (HW) return hmin(a, b);
+  else return vmin(a, b);
+}
 
 // A value with its location (relative to a known origin), for the arg
 // max/min filter.  Selection orders by value, then prefers the smaller
@@ -115,33 +137,34 @@ template <class T> __device__ __forceinline__ T readlane(T v, int lane) {
 }
 
 // Inclusive prefix (in lane order) of max and min over the 64-lane wave.
-template <class T> __device__ __forceinline__ void wave_prefix2(T& x, T& n) {
+// HW: select with hmax / hmin instead of vmax / vmin.
+template <class T, bool HW = false> __device__ __forceinline__ void wave_prefix2(T& x, T& n) {
   const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
-  x = vmax(x, dpp<0x111>(lo, x)); n = vmin(n, dpp<0x111>(hi, n));  // row_shr:1
-  x = vmax(x, dpp<0x112>(lo, x)); n = vmin(n, dpp<0x112>(hi, n));  // row_shr:2
-  x = vmax(x, dpp<0x114>(lo, x)); n = vmin(n, dpp<0x114>(hi, n));  // row_shr:4
-  x = vmax(x, dpp<0x118>(lo, x)); n = vmin(n, dpp<0x118>(hi, n));  // row_shr:8
+  x = smax<HW>(x, dpp<0x111>(lo, x)); n = smin<HW>(n, dpp<0x111>(hi, n));  // row_shr:1
+  x = smax<HW>(x, dpp<0x112>(lo, x)); n = smin<HW>(n, dpp<0x112>(hi, n));  // row_shr:2
+  x = smax<HW>(x, dpp<0x114>(lo, x)); n = smin<HW>(n, dpp<0x114>(hi, n));  // row_shr:4
+  x = smax<HW>(x, dpp<0x118>(lo, x)); n = smin<HW>(n, dpp<0x118>(hi, n));  // row_shr:8
   const int row = (threadIdx.x & 63) >> 4;
   const T x0 = readlane(x, 15), x1 = readlane(x, 31), x2 = readlane(x, 47);
   const T n0 = readlane(n, 15), n1 = readlane(n, 31), n2 = readlane(n, 47);
-  if (row >= 1) { x = vmax(x, x0); n = vmin(n, n0); }
-  if (row >= 2) { x = vmax(x, x1); n = vmin(n, n1); }
-  if (row >= 3) { x = vmax(x, x2); n = vmin(n, n2); }
+  if (row >= 1) { x = smax<HW>(x, x0); n = smin<HW>(n, n0); }
+  if (row >= 2) { x = smax<HW>(x, x1); n = smin<HW>(n, n1); }
+  if (row >= 3) { x = smax<HW>(x, x2); n = smin<HW>(n, n2); }
 }
 
 // Inclusive suffix (from the last lane down) of max and min over the wave.
-template <class T> __device__ __forceinline__ void wave_suffix2(T& x, T& n) {
+template <class T, bool HW = false> __device__ __forceinline__ void wave_suffix2(T& x, T& n) {
   const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
-  x = vmax(x, dpp<0x101>(lo, x)); n = vmin(n, dpp<0x101>(hi, n));  // row_shl:1
-  x = vmax(x, dpp<0x102>(lo, x)); n = vmin(n, dpp<0x102>(hi, n));  // row_shl:2
-  x = vmax(x, dpp<0x104>(lo, x)); n = vmin(n, dpp<0x104>(hi, n));  // row_shl:4
-  x = vmax(x, dpp<0x108>(lo, x)); n = vmin(n, dpp<0x108>(hi, n));  // row_shl:8
+  x = smax<HW>(x, dpp<0x101>(lo, x)); n = smin<HW>(n, dpp<0x101>(hi, n));  // row_shl:1
+  x = smax<HW>(x, dpp<0x102>(lo, x)); n = smin<HW>(n, dpp<0x102>(hi, n));  // row_shl:2
+  x = smax<HW>(x, dpp<0x104>(lo, x)); n = smin<HW>(n, dpp<0x104>(hi, n));  // row_shl:4
+  x = smax<HW>(x, dpp<0x108>(lo, x)); n = smin<HW>(n, dpp<0x108>(hi, n));  // row_shl:8
   const int row = (threadIdx.x & 63) >> 4;
   const T x1 = readlane(x, 16), x2 = readlane(x, 32), x3 = readlane(x, 48);
   const T n1 = readlane(n, 16), n2 = readlane(n, 32), n3 = readlane(n, 48);
-  if (row <= 2) { x = vmax(x, x3); n = vmin(n, n3); }
-  if (row <= 1) { x = vmax(x, x2); n = vmin(n, n2); }
-  if (row <= 0) { x = vmax(x, x1); n = vmin(n, n1); }
+  if (row <= 2) { x = smax<HW>(x, x3); n = smin<HW>(n, n3); }
+  if (row <= 1) { x = smax<HW>(x, x2); n = smin<HW>(n, n2); }
+  if (row <= 0) { x = smax<HW>(x, x1); n = smin<HW>(n, n1); }
 }
 
 // ---------------------------------------------------------------- series

@@ -527,8 +527,8 @@ __device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, Lds& sm) {
   constexpr int NW = kChunkThreads / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T ix = ax, in = an, jx = bx, jn = bn;
-  wave_prefix2(ix, in);
-  wave_suffix2(jx, jn);
+  wave_prefix2<T, true>(ix, in);
+  wave_suffix2<T, true>(jx, jn);
   if (lane == 63) {
     sm.red[0][wave] = ix;
     sm.red[1][wave] = in;
@@ -544,15 +544,15 @@ __device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, Lds& sm) {
 #pragma unroll
   for (int v = 0; v < NW; ++v) {
     const T r0 = sm.red[0][v], r1 = sm.red[1][v], r2 = sm.red[2][v], r3 = sm.red[3][v];
-    tx = vmax(tx, r0);
-    tn = vmin(tn, r1);
+    tx = hmax(tx, r0);
+    tn = hmin(tn, r1);
     if (v < wave) {
-      cpx = vmax(cpx, r0);
-      cpn = vmin(cpn, r1);
+      cpx = hmax(cpx, r0);
+      cpn = hmin(cpn, r1);
     }
     if (v > wave) {
-      csx = vmax(csx, r2);
-      csn = vmin(csn, r3);
+      csx = hmax(csx, r2);
+      csn = hmin(csn, r3);
     }
   }
   T ex = shup(ix, 1, 64), en = shup(in, 1, 64), fx = shdn(jx, 1, 64), fn = shdn(jn, 1, 64);
@@ -564,10 +564,10 @@ __device__ void wg_scan2(T& ax, T& an, T& bx, T& bn, T& tx, T& tn, Lds& sm) {
     fx = Lim<T>::lo();
     fn = Lim<T>::hi();
   }
-  ax = vmax(cpx, ex);
-  an = vmin(cpn, en);
-  bx = vmax(csx, fx);
-  bn = vmin(csn, fn);
+  ax = hmax(cpx, ex);
+  an = hmin(cpn, en);
+  bx = hmax(csx, fx);
+  bn = hmin(csn, fn);
 }
 
 // Per-thread inputs of a chunk tile: own positions p0 + r and the shifted
@@ -712,13 +712,13 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
 
 #pragma unroll
   for (int i = 1; i < V; ++i) {
-    ax[i] = vmax(ax[i - 1], ax[i]);
-    an[i] = vmin(an[i - 1], an[i]);
+    ax[i] = hmax(ax[i - 1], ax[i]);
+    an[i] = hmin(an[i - 1], an[i]);
   }
 #pragma unroll
   for (int i = V - 2; i >= 0; --i) {
-    bx[i] = vmax(bx[i + 1], bx[i]);
-    bn[i] = vmin(bn[i + 1], bn[i]);
+    bx[i] = hmax(bx[i + 1], bx[i]);
+    bn[i] = hmin(bn[i + 1], bn[i]);
   }
   T epx = ax[V - 1], epn = an[V - 1], esx = bx[0], esn = bn[0], tx, tn;
   wg_scan2<T>(epx, epn, esx, esn, tx, tn, sm);
@@ -735,20 +735,20 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
         if (!(base == u0 && K - 1 <= 64 && fok))
           fetch<T>(ring_slot(ring, gbase + u), ring_tag(ring, ep, gbase + u), mx, mn, ctl);
         if (u >= t - k) {
-          prx = vmax(prx, mx);
-          prn = vmin(prn, mn);
+          prx = hmax(prx, mx);
+          prn = hmin(prn, mn);
         } else {
-          sux = vmax(sux, mx);
-          sun = vmin(sun, mn);
+          sux = hmax(sux, mx);
+          sun = hmin(sun, mn);
         }
       }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
-      prx = vmax(prx, (T)__shfl_xor(prx, d, 64));
-      prn = vmin(prn, (T)__shfl_xor(prn, d, 64));
-      sux = vmax(sux, (T)__shfl_xor(sux, d, 64));
-      sun = vmin(sun, (T)__shfl_xor(sun, d, 64));
+      prx = hmax(prx, (T)__shfl_xor(prx, d, 64));
+      prn = hmin(prn, (T)__shfl_xor(prn, d, 64));
+      sux = hmax(sux, (T)__shfl_xor(sux, d, 64));
+      sun = hmin(sun, (T)__shfl_xor(sun, d, 64));
     }
     if (tid == 0) {
       sm.dep[0] = prx;
@@ -763,16 +763,16 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   if (tid == 0) next = add_agent32(counter, 1u);
   __syncthreads();
   if (has_out) {
-    const T prx = vmax(sm.dep[0], epx), prn = vmin(sm.dep[1], epn);
-    const T sux = vmax(sm.dep[2], esx), sun = vmin(sm.dep[3], esn);
+    const T prx = hmax(sm.dep[0], epx), prn = hmin(sm.dep[1], epn);
+    const T sux = hmax(sm.dep[2], esx), sun = hmin(sm.dep[3], esn);
     // stage outputs: window ending at p0+r -> slot r
     const int r0 = tid * V;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       const int r = r0 + i;
       if (r < len) {
-        sm.xs[lds_idx<T>(r)] = vmax(vmax(bx[i], sux), vmax(prx, ax[i]));
-        sm.hs[lds_idx<T>(r)] = vmin(vmin(bn[i], sun), vmin(prn, an[i]));
+        sm.xs[lds_idx<T>(r)] = hmax(hmax(bx[i], sux), hmax(prx, ax[i]));
+        sm.hs[lds_idx<T>(r)] = hmin(hmin(bn[i], sun), hmin(prn, an[i]));
       }
     }
     __syncthreads();

@@ -31,7 +31,7 @@ import numpy as np
 
 SEED_ROOT = 610046
 
-WORKLOAD_IDS = {"plain": 1, "large": 2, "image": 3, "batched": 4, "serving": 5,
+WORKLOAD_IDS = {"plain": 1, "large": 2, "image": 3, "batched": 4, "serving": 5, "envelope": 6,
                 "tests": 9}
 
 
