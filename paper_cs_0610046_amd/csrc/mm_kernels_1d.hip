@@ -338,8 +338,8 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       for (int i = 1; i < V; ++i) {
         const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
         const E c = elem(cur[i], pr0 + i, et);
-        px[i] = start ? c : vmax(px[i - 1], c);
-        pn[i] = start ? c : vmin(pn[i - 1], c);
+        px[i] = start ? c : hmax(px[i - 1], c);
+        pn[i] = start ? c : hmin(pn[i - 1], c);
       }
       if (m > 1) {
         // a block spans m aligned lanes: exclusive scan of the lane totals
@@ -347,16 +347,16 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         for (int d = 1; d < m; d <<= 1) {
           const E a = shup(ix, d, m), b = shup(in, d, m);
           if (lig >= d) {
-            ix = vmax(ix, a);
-            in = vmin(in, b);
+            ix = hmax(ix, a);
+            in = hmin(in, b);
           }
         }
         const E cx = shup(ix, 1, m), cn = shup(in, 1, m);
         if (lig > 0) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            px[i] = vmax(px[i], cx);
-            pn[i] = vmin(pn[i], cn);
+            px[i] = hmax(px[i], cx);
+            pn[i] = hmin(pn[i], cn);
           }
         }
       }
@@ -375,24 +375,24 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     for (int i = V - 2; i >= 0; --i) {
       const bool end = ((pr0 + i + 1) & (B - 1)) == 0;  // a block ends here
       const E c = elem(cur[i], pr0 + i, et);
-      ux[i] = end ? c : vmax(ux[i + 1], c);
-      un[i] = end ? c : vmin(un[i + 1], c);
+      ux[i] = end ? c : hmax(ux[i + 1], c);
+      un[i] = end ? c : hmin(un[i + 1], c);
     }
     if (m > 1) {
       E jx = ux[0], jn = un[0];
       for (int d = 1; d < m; d <<= 1) {
         const E a = shdn(jx, d, m), b = shdn(jn, d, m);
         if (lig + d < m) {
-          jx = vmax(jx, a);
-          jn = vmin(jn, b);
+          jx = hmax(jx, a);
+          jn = hmin(jn, b);
         }
       }
       const E cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
       if (lig < m - 1) {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-          ux[i] = vmax(ux[i], cx);
-          un[i] = vmin(un[i], cn);
+          ux[i] = hmax(ux[i], cx);
+          un[i] = hmin(un[i], cn);
         }
       }
     }
@@ -405,13 +405,13 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const int q = qr0 + i, e = q + w - 1;
-        E rx = vmax(sx[i], sm.pm[lds_idx<E>(e & (RING - 1))]);
-        E rn = vmin(sn[i], sm.pn[lds_idx<E>(e & (RING - 1))]);
+        E rx = hmax(sx[i], sm.pm[lds_idx<E>(e & (RING - 1))]);
+        E rn = hmin(sn[i], sm.pn[lds_idx<E>(e & (RING - 1))]);
         const int b1 = q >> lgB, b2 = e >> lgB;
         if (b2 >= b1 + 2) {
           const int mi = (((b1 + 2) << lgB) - 1) & (RING - 1);
-          rx = vmax(rx, sm.pm[lds_idx<E>(mi)]);
-          rn = vmin(rn, sm.pn[lds_idx<E>(mi)]);
+          rx = hmax(rx, sm.pm[lds_idx<E>(mi)]);
+          rn = hmin(rn, sm.pn[lds_idx<E>(mi)]);
         }
         ox[i] = rx;
         on[i] = rn;
