@@ -329,74 +329,79 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         if (p >= nout && p < s.n) gstore(s.carry + (p - nout), cur[i]);
       }
     }
-    // PRE of P_k into the ring
-    {
-      E px[V], pn[V];
-      px[0] = elem(cur[0], pr0, et);
-      pn[0] = px[0];
-#pragma unroll
-      for (int i = 1; i < V; ++i) {
-        const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
-        const E c = elem(cur[i], pr0 + i, et);
-        px[i] = start ? c : hmax(px[i - 1], c);
-        pn[i] = start ? c : hmin(pn[i - 1], c);
-      }
-      if (m > 1) {
-        // a block spans m aligned lanes: exclusive scan of the lane totals
-        E ix = px[V - 1], in = pn[V - 1];
-        for (int d = 1; d < m; d <<= 1) {
-          const E a = shup(ix, d, m), b = shup(in, d, m);
-          if (lig >= d) {
-            ix = hmax(ix, a);
-            in = hmin(in, b);
-          }
-        }
-        const E cx = shup(ix, 1, m), cn = shup(in, 1, m);
-        if (lig > 0) {
-#pragma unroll
-          for (int i = 0; i < V; ++i) {
-            px[i] = hmax(px[i], cx);
-            pn[i] = hmin(pn[i], cn);
-          }
-        }
-      }
-      const int slot = pr0 & (RING - 1);
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        sm.pm[lds_idx<E>(slot + i)] = px[i];
-        sm.pn[lds_idx<E>(slot + i)] = pn[i];
-      }
-    }
-    // SUF of P_k, kept for the next sub-tile's outputs
+    // A sub-tile past the last input (a run's tail sub-tile) only emits the
+    // windows of the one before; its own PRE and SUF are never read.
+    const bool live = R0 + (int64_t)k * TT < lim;
     E ux[V], un[V];
-    ux[V - 1] = elem(cur[V - 1], pr0 + V - 1, et);
-    un[V - 1] = ux[V - 1];
+    if (live) {
+      // PRE of P_k into the ring
+      {
+        E px[V], pn[V];
+        px[0] = elem(cur[0], pr0, et);
+        pn[0] = px[0];
 #pragma unroll
-    for (int i = V - 2; i >= 0; --i) {
-      const bool end = ((pr0 + i + 1) & (B - 1)) == 0;  // a block ends here
-      const E c = elem(cur[i], pr0 + i, et);
-      ux[i] = end ? c : hmax(ux[i + 1], c);
-      un[i] = end ? c : hmin(un[i + 1], c);
-    }
-    if (m > 1) {
-      E jx = ux[0], jn = un[0];
-      for (int d = 1; d < m; d <<= 1) {
-        const E a = shdn(jx, d, m), b = shdn(jn, d, m);
-        if (lig + d < m) {
-          jx = hmax(jx, a);
-          jn = hmin(jn, b);
+        for (int i = 1; i < V; ++i) {
+          const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
+          const E c = elem(cur[i], pr0 + i, et);
+          px[i] = start ? c : hmax(px[i - 1], c);
+          pn[i] = start ? c : hmin(pn[i - 1], c);
         }
-      }
-      const E cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
-      if (lig < m - 1) {
+        if (m > 1) {
+          // a block spans m aligned lanes: exclusive scan of the lane totals
+          E ix = px[V - 1], in = pn[V - 1];
+          for (int d = 1; d < m; d <<= 1) {
+            const E a = shup(ix, d, m), b = shup(in, d, m);
+            if (lig >= d) {
+              ix = hmax(ix, a);
+              in = hmin(in, b);
+            }
+          }
+          const E cx = shup(ix, 1, m), cn = shup(in, 1, m);
+          if (lig > 0) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+              px[i] = hmax(px[i], cx);
+              pn[i] = hmin(pn[i], cn);
+            }
+          }
+        }
+        const int slot = pr0 & (RING - 1);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-          ux[i] = hmax(ux[i], cx);
-          un[i] = hmin(un[i], cn);
+          sm.pm[lds_idx<E>(slot + i)] = px[i];
+          sm.pn[lds_idx<E>(slot + i)] = pn[i];
         }
       }
+      // SUF of P_k, kept for the next sub-tile's outputs
+      ux[V - 1] = elem(cur[V - 1], pr0 + V - 1, et);
+      un[V - 1] = ux[V - 1];
+#pragma unroll
+      for (int i = V - 2; i >= 0; --i) {
+        const bool end = ((pr0 + i + 1) & (B - 1)) == 0;  // a block ends here
+        const E c = elem(cur[i], pr0 + i, et);
+        ux[i] = end ? c : hmax(ux[i + 1], c);
+        un[i] = end ? c : hmin(un[i + 1], c);
+      }
+      if (m > 1) {
+        E jx = ux[0], jn = un[0];
+        for (int d = 1; d < m; d <<= 1) {
+          const E a = shdn(jx, d, m), b = shdn(jn, d, m);
+          if (lig + d < m) {
+            jx = hmax(jx, a);
+            jn = hmin(jn, b);
+          }
+        }
+        const E cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
+        if (lig < m - 1) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            ux[i] = hmax(ux[i], cx);
+            un[i] = hmin(un[i], cn);
+          }
+        }
+      }
+      __syncthreads();  // PRE of P_k visible
     }
-    __syncthreads();  // PRE of P_k visible
     if (k > 0) {
       // windows starting in P_{k-1}: SUF (registers), PRE at the window end
       // and the whole block strictly inside, if any (both from the ring)
@@ -436,8 +441,10 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      sx[i] = ux[i];
-      sn[i] = un[i];
+      if (live) {
+        sx[i] = ux[i];
+        sn[i] = un[i];
+      }
       cur[i] = nxt[i];
     }
     __syncthreads();  // ring slots of P_{k-1} may now be reused by P_{k+1}
@@ -938,14 +945,67 @@ __global__ __launch_bounds__(256) void k_env_ends(const T* a, int64_t n, int64_t
   env_end<T>(a, n, r, up, lo, blockIdx.x == 0, sx, sn);
 }
 
-// series k = blockIdx.x + j * gridDim.x; blockIdx.y: 0 left end, 1 right end
+// The same end scan by one wavefront (no barriers), for the many short ends
+// of a batch: passes of 512 elements with a running carry.
+template <class T>
+__device__ void env_end_wave(const T* a, int64_t n, int64_t r, T* up, T* lo, bool left) {
+  constexpr int V = 8, WT = 64 * V;
+  const int lane = threadIdx.x & 63;
+  const int64_t m = min(n, 2 * r);
+  T cx = Lim<T>::lo(), cn = Lim<T>::hi();
+  for (int64_t base = 0; base < m; base += WT) {
+    T px[V], pn[V];
+    T rx = Lim<T>::lo(), rn = Lim<T>::hi();
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int64_t k = base + lane * V + i;
+      if (k < m) {
+        const T v = gload(a + (left ? k : n - 1 - k));
+        rx = vmax(rx, v);
+        rn = vmin(rn, v);
+      }
+      px[i] = rx;
+      pn[i] = rn;
+    }
+    T ix = rx, in = rn;
+    wave_prefix2(ix, in);
+    T ex = shup(ix, 1, 64), en = shup(in, 1, 64);
+    if (lane == 0) {
+      ex = Lim<T>::lo();
+      en = Lim<T>::hi();
+    }
+    const T tx = readlane(ix, 63), tn = readlane(in, 63);
+    const T ox = vmax(cx, ex), on = vmin(cn, en);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int64_t k = base + lane * V + i;
+      if (k < m && k >= r) {
+        const int64_t o = left ? k - r : n - 1 - k + r;
+        gstore(up + o, vmax(ox, px[i]));
+        gstore(lo + o, vmin(on, pn[i]));
+      }
+    }
+    cx = vmax(cx, tx);
+    cn = vmin(cn, tn);
+  }
+  if (left && m == n) {
+    for (int64_t i = max((int64_t)0, n - r) + lane; i < min(r, n); i += 64) {
+      gstore(up + i, cx);
+      gstore(lo + i, cn);
+    }
+  }
+}
+
+// one wavefront per series end: end e = global wave id, series e / 2, side
+// e % 2 (0 left, 1 right)
 template <class T>
 __global__ __launch_bounds__(256) void k_env_ends_batched(const T* in, const int64_t* off, const int64_t* radii,
                                                           int64_t S, T* up, T* lo) {
-  __shared__ T sx[4], sn[4];
-  for (int64_t k = blockIdx.x; k < S; k += gridDim.x) {
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); e < 2 * S; e += nw) {
+    const int64_t k = e >> 1;
     const int64_t s0 = off[k], n = off[k + 1] - s0, r = radii[k];
-    if (r > 0 && n > 0) env_end<T>(in + s0, n, r, up + s0, lo + s0, blockIdx.y == 0, sx, sn);
+    if (r > 0 && n > 0) env_end_wave<T>(in + s0, n, r, up + s0, lo + s0, (e & 1) == 0);
   }
 }
 
@@ -1165,24 +1225,47 @@ __global__ __launch_bounds__(kChunkThreads) void k_crun(Job<T> job) {
 }
 
 // ================================================================ batched
-// One workgroup: series descriptors, per-strategy tile counts and their
-// exclusive prefix sums (entry S holds the total).
+// Pass 1 (many workgroups): the series descriptors, and each series' tile
+// count for its strategy, written into the prefix arrays (scanned in pass 2).
 template <class T>
-__global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int64_t* in_off,
-                                                        const int64_t* wins, const int64_t* out_off,
-                                                        int64_t S, T* d_max, T* d_min, Series<T>* descs,
-                                                        int64_t* pre_tile, int64_t* pre_chunk, int64_t run) {
+__global__ __launch_bounds__(256) void k_batched_count(const T* d_in, const int64_t* in_off, const int64_t* wins,
+                                                       const int64_t* out_off, int64_t S, T* d_max, T* d_min,
+                                                       Series<T>* descs, int64_t* pre_tile, int64_t* pre_chunk,
+                                                       int64_t run) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S; k += stride) {
+    const int64_t n = in_off[k + 1] - in_off[k], w = wins[k];
+    Series<T> d;
+    d.a = d_in + in_off[k];
+    d.b = nullptr;
+    d.na = n;
+    d.n = n;
+    d.w = w;
+    d.omax = d_max ? d_max + out_off[k] : nullptr;
+    d.omin = d_min ? d_min + out_off[k] : nullptr;
+    d.carry = nullptr;
+    descs[k] = d;
+    int64_t ct = 0, cc = 0;
+    if (w >= 1 && n > 0) {
+      if (w <= kTileMaxW) ct = run_count(n, w, run);
+      else cc = chunk_count(n, w);
+    }
+    pre_tile[k] = ct;
+    pre_chunk[k] = cc;
+  }
+}
+
+// Pass 2 (one workgroup): exclusive prefix sums of both count arrays in
+// place; entry S receives the total.
+__global__ __launch_bounds__(1024) void k_batched_scan(int64_t S, int64_t* pre_tile, int64_t* pre_chunk) {
   __shared__ int64_t st[1024], sc[1024];
   const int tid = threadIdx.x, NTH = blockDim.x;
   const int64_t per = (S + NTH - 1) / NTH;
   const int64_t k0 = min(S, (int64_t)tid * per), k1 = min(S, k0 + per);
   int64_t a = 0, c = 0;
   for (int64_t k = k0; k < k1; ++k) {
-    const int64_t n = in_off[k + 1] - in_off[k], w = wins[k];
-    if (w >= 1 && n > 0) {
-      if (w <= kTileMaxW) a += run_count(n, w, run);
-      else c += chunk_count(n, w);
-    }
+    a += pre_tile[k];
+    c += pre_chunk[k];
   }
   st[tid] = a;
   sc[tid] = c;
@@ -1196,23 +1279,11 @@ __global__ __launch_bounds__(1024) void k_batched_setup(const T* d_in, const int
   }
   int64_t ra = st[tid] - a, rc = sc[tid] - c;  // exclusive
   for (int64_t k = k0; k < k1; ++k) {
-    const int64_t n = in_off[k + 1] - in_off[k], w = wins[k];
-    Series<T> d;
-    d.a = d_in + in_off[k];
-    d.b = nullptr;
-    d.na = n;
-    d.n = n;
-    d.w = w;
-    d.omax = d_max ? d_max + out_off[k] : nullptr;
-    d.omin = d_min ? d_min + out_off[k] : nullptr;
-    d.carry = nullptr;
-    descs[k] = d;
+    const int64_t ta = pre_tile[k], tc = pre_chunk[k];
     pre_tile[k] = ra;
     pre_chunk[k] = rc;
-    if (w >= 1 && n > 0) {
-      if (w <= kTileMaxW) ra += run_count(n, w, run);
-      else rc += chunk_count(n, w);
-    }
+    ra += ta;
+    rc += tc;
   }
   if (tid == NTH - 1) {
     pre_tile[S] = st[NTH - 1];
@@ -1346,8 +1417,12 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
                                 int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st) {
   return dispatch(dtype, [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
-    hipLaunchKernelGGL(k_batched_setup<T>, dim3(1), dim3(1024), 0, st, (const T*)d_in, in_off, wins, out_off, S,
+    const int g = (int)std::min<int64_t>((S + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_batched_count<T>, dim3(g), dim3(256), 0, st, (const T*)d_in, in_off, wins, out_off, S,
                        (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk, (int64_t)kRunBatched);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batched_scan, dim3(1), dim3(1024), 0, st, S, pre_tile, pre_chunk);
     return hipGetLastError();
   });
 }
@@ -1381,10 +1456,10 @@ hipError_t launch_env_batched(int dtype, const void* in, const int64_t* off, con
     hipLaunchKernelGGL(k_env_setup, dim3(g), dim3(256), 0, st, off, radii, S, wins, oo);
     return hipGetLastError();
   }
-  const int g = (int)std::min<int64_t>(S, 65535);
+  const int g = (int)std::min<int64_t>((2 * S + 3) / 4, (int64_t)cu_count() * 32);
   return dispatch(dtype, [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
-    hipLaunchKernelGGL(k_env_ends_batched<T>, dim3(g, 2), dim3(256), 0, st, (const T*)in, off, radii, S, (T*)up,
+    hipLaunchKernelGGL(k_env_ends_batched<T>, dim3(g), dim3(256), 0, st, (const T*)in, off, radii, S, (T*)up,
                        (T*)lo);
     return hipGetLastError();
   });
