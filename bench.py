@@ -45,7 +45,8 @@ def alg_bytes(n, w, s):
 
 
 def kernel_name(strategy):
-    return "mm::k_%s<0, float>" % strategy
+    # as rocprofv3 names the single-series float32 instantiations
+    return "mm::k_tile<0, float, false>" if strategy == "tile" else "mm::k_%s<0, float>" % strategy
 
 
 # Sources whose change invalidates counter-derived traffic figures.
