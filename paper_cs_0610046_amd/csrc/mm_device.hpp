@@ -185,6 +185,82 @@ template <class T, bool HW = false> __device__ __forceinline__ void wave_suffix2
   if (row <= 0) { x = smax<HW>(x, x1); n = smin<HW>(n, n1); }
 }
 
+// Inclusive scans of (max, min) over aligned groups of m lanes (m a power of
+// two in 2..64, the same in every lane; lig = lane & (m-1)): prefix in lane
+// order, or suffix.  DPP row shifts inside the 16-lane rows (a lane whose
+// source lies in another group keeps its value), readlane across rows.
+template <class T, bool HW>
+__device__ __forceinline__ void seg_prefix2(T& x, T& n, int m, int lig) {
+  const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
+  T a = dpp<0x111>(lo, x), b = dpp<0x111>(hi, n);  // row_shr:1
+  x = lig >= 1 ? smax<HW>(x, a) : x;
+  n = lig >= 1 ? smin<HW>(n, b) : n;
+  if (m > 2) {
+    a = dpp<0x112>(lo, x), b = dpp<0x112>(hi, n);  // row_shr:2
+    x = lig >= 2 ? smax<HW>(x, a) : x;
+    n = lig >= 2 ? smin<HW>(n, b) : n;
+  }
+  if (m > 4) {
+    a = dpp<0x114>(lo, x), b = dpp<0x114>(hi, n);  // row_shr:4
+    x = lig >= 4 ? smax<HW>(x, a) : x;
+    n = lig >= 4 ? smin<HW>(n, b) : n;
+  }
+  if (m > 8) {
+    a = dpp<0x118>(lo, x), b = dpp<0x118>(hi, n);  // row_shr:8
+    x = lig >= 8 ? smax<HW>(x, a) : x;
+    n = lig >= 8 ? smin<HW>(n, b) : n;
+  }
+  if (m > 16) {
+    const int row = (threadIdx.x & 63) >> 4;
+    const T x0 = readlane(x, 15), x1 = readlane(x, 31), x2 = readlane(x, 47);
+    const T n0 = readlane(n, 15), n1 = readlane(n, 31), n2 = readlane(n, 47);
+    if (m == 32) {
+      // groups: rows 0-1 and rows 2-3
+      if (row == 1) { x = smax<HW>(x, x0); n = smin<HW>(n, n0); }
+      if (row == 3) { x = smax<HW>(x, x2); n = smin<HW>(n, n2); }
+    } else {
+      if (row >= 1) { x = smax<HW>(x, x0); n = smin<HW>(n, n0); }
+      if (row >= 2) { x = smax<HW>(x, x1); n = smin<HW>(n, n1); }
+      if (row >= 3) { x = smax<HW>(x, x2); n = smin<HW>(n, n2); }
+    }
+  }
+}
+template <class T, bool HW>
+__device__ __forceinline__ void seg_suffix2(T& x, T& n, int m, int lig) {
+  const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
+  T a = dpp<0x101>(lo, x), b = dpp<0x101>(hi, n);  // row_shl:1
+  x = lig + 1 < m ? smax<HW>(x, a) : x;
+  n = lig + 1 < m ? smin<HW>(n, b) : n;
+  if (m > 2) {
+    a = dpp<0x102>(lo, x), b = dpp<0x102>(hi, n);  // row_shl:2
+    x = lig + 2 < m ? smax<HW>(x, a) : x;
+    n = lig + 2 < m ? smin<HW>(n, b) : n;
+  }
+  if (m > 4) {
+    a = dpp<0x104>(lo, x), b = dpp<0x104>(hi, n);  // row_shl:4
+    x = lig + 4 < m ? smax<HW>(x, a) : x;
+    n = lig + 4 < m ? smin<HW>(n, b) : n;
+  }
+  if (m > 8) {
+    a = dpp<0x108>(lo, x), b = dpp<0x108>(hi, n);  // row_shl:8
+    x = lig + 8 < m ? smax<HW>(x, a) : x;
+    n = lig + 8 < m ? smin<HW>(n, b) : n;
+  }
+  if (m > 16) {
+    const int row = (threadIdx.x & 63) >> 4;
+    const T x1 = readlane(x, 16), x2 = readlane(x, 32), x3 = readlane(x, 48);
+    const T n1 = readlane(n, 16), n2 = readlane(n, 32), n3 = readlane(n, 48);
+    if (m == 32) {
+      if (row == 0) { x = smax<HW>(x, x1); n = smin<HW>(n, n1); }
+      if (row == 2) { x = smax<HW>(x, x3); n = smin<HW>(n, n3); }
+    } else {
+      if (row <= 2) { x = smax<HW>(x, x3); n = smin<HW>(n, n3); }
+      if (row <= 1) { x = smax<HW>(x, x2); n = smin<HW>(n, n2); }
+      if (row <= 0) { x = smax<HW>(x, x1); n = smin<HW>(n, n1); }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- series
 // One series of the 1-D filter.  Its n elements are the concatenation of two
 // segments: element i is a[i] for i < na, else b[i - na].  A plain call has

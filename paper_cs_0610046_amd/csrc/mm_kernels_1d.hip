@@ -349,14 +349,22 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         if (m > 1) {
           // a block spans m aligned lanes: exclusive scan of the lane totals
           E ix = px[V - 1], in = pn[V - 1];
-          for (int d = 1; d < m; d <<= 1) {
-            const E a = shup(ix, d, m), b = shup(in, d, m);
-            if (lig >= d) {
-              ix = hmax(ix, a);
-              in = hmin(in, b);
+          E cx, cn;
+          if constexpr (!ARG) {
+            seg_prefix2<T, true>(ix, in, m, lig);
+            cx = dpp<0x138>(Lim<T>::lo(), ix);  // wave_shr:1 (read only where lig > 0)
+            cn = dpp<0x138>(Lim<T>::hi(), in);
+          } else {
+            for (int d = 1; d < m; d <<= 1) {
+              const E a = shup(ix, d, m), b = shup(in, d, m);
+              if (lig >= d) {
+                ix = hmax(ix, a);
+                in = hmin(in, b);
+              }
             }
+            cx = shup(ix, 1, m);
+            cn = shup(in, 1, m);
           }
-          const E cx = shup(ix, 1, m), cn = shup(in, 1, m);
           if (lig > 0) {
 #pragma unroll
             for (int i = 0; i < V; ++i) {
@@ -384,14 +392,22 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       }
       if (m > 1) {
         E jx = ux[0], jn = un[0];
-        for (int d = 1; d < m; d <<= 1) {
-          const E a = shdn(jx, d, m), b = shdn(jn, d, m);
-          if (lig + d < m) {
-            jx = hmax(jx, a);
-            jn = hmin(jn, b);
+        E cx, cn;
+        if constexpr (!ARG) {
+          seg_suffix2<T, true>(jx, jn, m, lig);
+          cx = dpp<0x130>(Lim<T>::lo(), jx);  // wave_shl:1 (read only where lig < m-1)
+          cn = dpp<0x130>(Lim<T>::hi(), jn);
+        } else {
+          for (int d = 1; d < m; d <<= 1) {
+            const E a = shdn(jx, d, m), b = shdn(jn, d, m);
+            if (lig + d < m) {
+              jx = hmax(jx, a);
+              jn = hmin(jn, b);
+            }
           }
+          cx = shdn(jx, 1, m);
+          cn = shdn(jn, 1, m);
         }
-        const E cx = shdn(jx, 1, m), cn = shdn(jn, 1, m);
         if (lig < m - 1) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
