@@ -58,6 +58,7 @@ bool aligned(const void* p, size_t s) { return ((uintptr_t)p % s) == 0; }
 
 std::atomic<int> g_force{0};
 constexpr int kDefaultChunkRanges = 16;
+constexpr int kDefaultChunkRangesLong = 0;
 
 int env_strategy() {
   static int v = -1;
@@ -230,11 +231,13 @@ int ensure_buf(Workspace* ws, void** buf, size_t* have, size_t bytes) {
 int ensure_tmp(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp, &ws->tmp_bytes, bytes); }
 int ensure_tmp2(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp2, &ws->tmp2_bytes, bytes); }
 
-// Ticket ranges for a single-series chunk launch (0, 1, 8, 16 or 32); the
-// environment variable MAXMIN_CHUNK_RANGES overrides the default.
-int chunk_ranges() {
-  int v = kDefaultChunkRanges;
-  const char* e = getenv("MAXMIN_CHUNK_RANGES");
+// Ticket ranges for a single-series chunk launch (0, 1, 8, 16 or 32), for
+// one-chunk windows (w <= 4096) and for longer ones; the environment
+// variables MAXMIN_CHUNK_RANGES and MAXMIN_CHUNK_RANGES_LONG override them.
+int chunk_ranges(int64_t w) {
+  const bool one = w <= mm::kChunkMax;
+  int v = one ? kDefaultChunkRanges : kDefaultChunkRangesLong;
+  const char* e = getenv(one ? "MAXMIN_CHUNK_RANGES" : "MAXMIN_CHUNK_RANGES_LONG");
   if (e) {
     const int x = atoi(e);
     if (x == 0 || x == 1 || x == 8 || x == 16 || x == 32) v = x;
@@ -271,7 +274,7 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     a.ring = ws->ring;
     a.ring_lg = ws->ring_lg;
     a.ctl = ws->ctl;
-    a.ranges = chunk_ranges();
+    a.ranges = chunk_ranges(a.w);
     const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratChunk));
     e = mm::launch_1d(dt, mm::kStratChunk, a, grid, st);
   }

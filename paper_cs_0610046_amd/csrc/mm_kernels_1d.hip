@@ -686,7 +686,7 @@ __device__ __forceinline__ void chunk_store(T* out, const T* buf, int rs, int le
 // counter: where the next ticket comes from.
 template <class T>
 __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const FlagRing& ring, uint32_t ep,
-                           ChunkLds<T>& sm, Ctl* ctl, uint32_t* counter, uint32_t& next) {
+                           ChunkLds<T>& sm, Ctl* ctl, uint32_t* counter, uint32_t& next, bool warm = false) {
   constexpr int V = kChunkV;
   const int tid = threadIdx.x;
   const int64_t w = s.w, n = s.n;
@@ -696,8 +696,10 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   const int64_t p0 = b * w + k * C;  // first input of the owned chunk
   const int lenfull = (int)min(C, w - k * C);
   const int len = (int)min((int64_t)lenfull, n - p0);
-  const bool behind = b >= 1;
-  const bool has_out = (p0 + len - 1) >= (w - 1);
+  // warm: a chunk just before this workgroup's ticket range, redone only to
+  // publish its aggregate for the range's first chunks (no outputs)
+  const bool behind = b >= 1 && !warm;
+  const bool has_out = !warm && (p0 + len - 1) >= (w - 1);
 
   T ax[V], an[V], bx[V], bn[V];
   chunk_load<T>(s, p0, w, len, lenfull, behind, ax, an, bx, bn);
@@ -812,18 +814,23 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   Ctl* ctl = job.ctl;
   const uint32_t ep = ld_agent32(&ctl->epoch);
   const int64_t ntiles = job_tiles<MODE>(job);
-  // A single series with one chunk per window (K = 1: no look-back) may
-  // split into R contiguous ranges of chunks, each with its own in-order
-  // tickets and served by the workgroups with blockIdx % R equal to its
-  // number.  Workgroup ids go round robin over the 8 XCDs, so with R a
-  // multiple of 8 a range stays on one XCD, and the chunk w back that each
-  // chunk re-reads was loaded there a moment earlier and is still in that
-  // XCD's L2.  The placement matters for speed only.  (With K > 1 the
-  // look-back chains ran slower split than whole on MI355X.)
+  // A single series may split into R contiguous ranges of chunks, each with
+  // its own in-order tickets and served by the workgroups with blockIdx % R
+  // equal to its number.  Workgroup ids go round robin over the 8 XCDs, so
+  // with R a multiple of 8 a range stays on one XCD, and the chunk w back
+  // that each chunk re-reads was loaded there a moment earlier and is still
+  // in that XCD's L2.  The placement matters for speed only.  With K > 1 a
+  // range first redoes the K-1 chunks before it (loads and publishes their
+  // aggregates, identical to what the range before publishes), so its first
+  // chunks wait only on its own workgroups; this needs every chunk of the
+  // launch to own a ring slot.
   const int R = MODE == kJobOne ? job.ranges : 0;
-  const bool split = R > 1 && ntiles >= 32 * (int64_t)R && (int)gridDim.x >= 8 * R && job.one.w <= kChunkMax;
+  const int64_t K1 = MODE == kJobOne ? (job.one.w + kChunkMax - 1) / kChunkMax : 1;
+  const bool split = R > 1 && ntiles >= 32 * (int64_t)R && (int)gridDim.x >= 8 * R && K1 <= 64 &&
+                     (K1 == 1 || ntiles <= (int64_t(1) << job.ring.lg));
   const int cls = split ? (int)(blockIdx.x % R) : 0;
   const int64_t rlo = split ? ntiles * cls / R : 0, rhi = split ? ntiles * (cls + 1) / R : ntiles;
+  const int64_t rfirst = split ? max((int64_t)0, rlo - (K1 - 1)) : 0;  // first ticketed chunk
   uint32_t* counter = split ? &ctl->tick[cls][0] : &ctl->ticket;
   // thread 0 takes each next ticket while the current chunk stores its outputs
   uint32_t next = 0;
@@ -831,11 +838,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   for (;;) {
     if (threadIdx.x == 0) sm.ticket = next;
     __syncthreads();
-    const int64_t t = rlo + (int64_t)sm.ticket;
+    const int64_t t = rfirst + (int64_t)sm.ticket;
     if (t >= rhi) break;
     int64_t local, gbase;
     const Series<T> s = job_series<MODE>(job, t, local, gbase);
-    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl, counter, next);
+    chunk_body<T>(s, local, gbase, job.ring, ep, sm, ctl, counter, next, t < rlo);
   }
   // the last workgroup out re-arms the control words for the next launch
   if (threadIdx.x == 0) {

@@ -128,13 +128,16 @@ def test_large_windows(strategy):
 
 @pytest.mark.parametrize("ranges", ["0", "8", "16", "32"])
 def test_chunk_ticket_ranges(ranges, monkeypatch):
-    """One-chunk windows (1024 < w <= 4096) split the chunks of a series
-    into per-XCD ticket ranges; every range count gives the oracle's bits,
+    """The chunks of a series split into per-XCD ticket ranges (one-chunk
+    windows 1024 < w <= 4096, and longer windows whose ranges first redo the
+    chunks just before them); every range count gives the oracle's bits,
     with chunk counts that do not divide evenly into the ranges."""
     monkeypatch.setenv("MAXMIN_CHUNK_RANGES", ranges)
+    monkeypatch.setenv("MAXMIN_CHUNK_RANGES_LONG", ranges)
     rng = synth.rng_for("tests", 106)
     for dt in (np.float32, np.float64):
-        for w, n in ((1025, 1100003), (1500, 1500 * 700 + 311), (4096, 4096 * 1031 + 4095)):
+        for w, n in ((1025, 1100003), (1500, 1500 * 700 + 311), (4096, 4096 * 1031 + 4095),
+                     (5000, 2500 * 1400 + 77), (9000, 3000 * 1500 + 1234), (65536, 4096 * 1100 + 999)):
             a = gen(n, dt, rng, "walk")
             note("ranges=%s dt=%s n=%d w=%d" % (ranges, np.dtype(dt).name, n, w))
             check(a, w, "ranges=%s n=%d w=%d" % (ranges, n, w))
