@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--n-log2", type=int, default=28)
     ap.add_argument("--extras", type=int, default=1, help="also run plain / batched / image workloads")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--autotune", type=int, default=1, help="measure the planner's launch parameters first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (a known-size kernel for counter calibration)")
     args = ap.parse_args()
@@ -124,6 +125,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuning = mm.maxmin_tuning(torch.float32)
+    if args.autotune:
+        t0 = time.time()
+        tuning = mm.maxmin_autotune(torch.float32, 1 << 26)
+        print("[bench] autotune %.2fs: %s" % (time.time() - t0, tuning), file=sys.stderr, flush=True)
     n = 1 << args.n_log2
     t0 = time.time()
     a = synth.random_walk(n, np.float32, synth.rng_for("large", 0))
@@ -209,7 +215,7 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "single float32 random walk n=2^%d, windows %s" % (args.n_log2, list(WINDOWS)),
                        "n": n, "windows": list(WINDOWS)},
-            "per_window": per_window, "roofline": roofline, "cpu_baseline": cpu}
+            "per_window": per_window, "roofline": roofline, "cpu_baseline": cpu, "tuning": tuning}
     line.update(extras)
     print(json.dumps(line), flush=True)
 

@@ -51,6 +51,8 @@ def lib():
         L.maxmin_stream_samples.restype = i64
         L.maxmin_filter_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, vp, vp, i64, vp]
         L.maxmin_morph_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, ci, vp, i64, vp]
+        L.maxmin_autotune.argtypes = [ci, i64, vp]
+        L.maxmin_tuning.argtypes = [ci, i64p]
         L.maxmin_envelope.argtypes = [ci, vp, i64, i64, vp, vp, vp]
         L.maxmin_envelope_batched.argtypes = [ci, vp, vp, vp, i64, vp, vp, vp]
         L.maxmin_set_strategy.argtypes = [ci]
@@ -77,7 +79,7 @@ def lib():
         L.maxmin_version.restype = ctypes.c_char_p
         for f in ("maxmin_filter", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
                   "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_morph_2d",
-                  "maxmin_envelope", "maxmin_envelope_batched",
+                  "maxmin_envelope", "maxmin_envelope_batched", "maxmin_autotune", "maxmin_tuning",
                   "maxmin_set_strategy",
                   "maxmin_plan", "maxmin_check_stream"):
             getattr(L, f).restype = ci
@@ -297,6 +299,22 @@ def maxmin_envelope_batched(packed, in_offsets, radii, out_upper=None, out_lower
     _check(lib().maxmin_envelope_batched(dtype_code(packed.dtype), _ptr(packed), _ptr(in_offsets), _ptr(radii),
                                          radii.numel(), _ptr(out_upper), _ptr(out_lower), _stream(stream)))
     return out_upper, out_lower
+
+
+def maxmin_autotune(dtype, n=0, stream=None):
+    """Measure the planner's launch parameters for ``dtype`` on this device
+    (process-wide) and return the resulting table (see :func:`maxmin_tuning`)."""
+    _check(lib().maxmin_autotune(dtype_code(dtype), int(n), _stream(stream)))
+    return maxmin_tuning(dtype)
+
+
+def maxmin_tuning(dtype):
+    """The planner's launch parameters for ``dtype`` (host only)."""
+    out = (ctypes.c_int64 * 6)()
+    _check(lib().maxmin_tuning(dtype_code(dtype), out))
+    return {"tile_run_subtiles": out[0], "batched_run_subtiles": out[1], "chunk_ranges_one_chunk": out[2],
+            "chunk_ranges_long": out[3], "long_window_strategy": {2: "chunk", 3: "run"}.get(out[4], out[4]),
+            "measured": bool(out[5])}
 
 
 MORPH_OPS = {"erode": 0, "dilate": 1, "open": 2, "close": 3}

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -57,8 +59,24 @@ size_t dsize(int dt) {
 bool aligned(const void* p, size_t s) { return ((uintptr_t)p % s) == 0; }
 
 std::atomic<int> g_force{0};
-constexpr int kDefaultChunkRanges = 16;
-constexpr int kDefaultChunkRangesLong = 0;
+
+// Launch parameters the planner uses, per dtype.  The defaults are the
+// choices measured best on MI355X; maxmin_autotune re-measures them on the
+// device at hand.  Environment variables still override (experiments).
+struct Tuning {
+  int tile_run = 16;     // sub-tiles per run, single-series tile launches
+  int batched_run = 16;  // sub-tiles per run, batched and 2-D row launches
+  int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096)
+  int ranges_long = 0;   // chunk ticket ranges, longer windows
+  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 1024: chunk or run
+  int tuned = 0;
+};
+std::mutex g_tune_mu;
+Tuning g_tune[4];
+Tuning tuning(int dt) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_tune[dt >= 0 && dt < 4 ? dt : 0];
+}
 
 int env_strategy() {
   static int v = -1;
@@ -84,18 +102,19 @@ int64_t run_chunks_per_run(int dt, int64_t n, int64_t w) {
 // n = 2^28 float32 they ran slower than look-back chunks at w = 4096 and 8192
 // (1.46 ms against 0.83 and 0.88 ms).
 int plan_strategy(int dt, int64_t n, int64_t w) {
-  (void)dt;
   (void)n;
   int f = g_force.load();
   if (!f) f = env_strategy();
+  const bool run_ok = (w + mm::kCrMax - 1) / mm::kCrMax <= mm::kCrRing;
   if (f == MAXMIN_STRATEGY_CHUNK) return MAXMIN_STRATEGY_CHUNK;
-  if (f == MAXMIN_STRATEGY_RUN && (w + mm::kCrMax - 1) / mm::kCrMax <= mm::kCrRing) return MAXMIN_STRATEGY_RUN;
+  if (f == MAXMIN_STRATEGY_RUN && run_ok) return MAXMIN_STRATEGY_RUN;
   if (w <= mm::kTileMaxW) return MAXMIN_STRATEGY_TILE;
+  if (!f && run_ok && tuning(dt).long_strategy == MAXMIN_STRATEGY_RUN) return MAXMIN_STRATEGY_RUN;
   return MAXMIN_STRATEGY_CHUNK;
 }
 
 // ------------------------------------------------------------ workspaces
-typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*> GraphKey;
+typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*, int64_t> GraphKey;
 
 struct Workspace {
   int device = 0;
@@ -234,9 +253,10 @@ int ensure_tmp2(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp2, 
 // Ticket ranges for a single-series chunk launch (0, 1, 8, 16 or 32), for
 // one-chunk windows (w <= 4096) and for longer ones; the environment
 // variables MAXMIN_CHUNK_RANGES and MAXMIN_CHUNK_RANGES_LONG override them.
-int chunk_ranges(int64_t w) {
+int chunk_ranges(int dt, int64_t w) {
   const bool one = w <= mm::kChunkMax;
-  int v = one ? kDefaultChunkRanges : kDefaultChunkRangesLong;
+  const Tuning t = tuning(dt);
+  int v = one ? t.ranges_one : t.ranges_long;
   const char* e = getenv(one ? "MAXMIN_CHUNK_RANGES" : "MAXMIN_CHUNK_RANGES_LONG");
   if (e) {
     const int x = atoi(e);
@@ -251,7 +271,7 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
     const int cap = mm::grid_cap(dt, mm::kStratTile);
-    a.run = mm::run_length(a.n - a.w + 1, cap);
+    a.run = mm::run_length(a.n - a.w + 1, cap, (int64_t)tuning(dt).tile_run * mm::kTileOut);
     if (const char* e = getenv("MAXMIN_TILE_RUN")) {
       const int64_t r = atoll(e) / mm::kTileOut * mm::kTileOut;
       if (r > 0 && r < a.run) a.run = r;
@@ -274,7 +294,7 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     a.ring = ws->ring;
     a.ring_lg = ws->ring_lg;
     a.ctl = ws->ctl;
-    a.ranges = chunk_ranges(a.w);
+    a.ranges = chunk_ranges(dt, a.w);
     const int grid = (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dt, mm::kStratChunk));
     e = mm::launch_1d(dt, mm::kStratChunk, a, grid, st);
   }
@@ -442,18 +462,19 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
   if ((r = ensure_batch(ws, S))) return r;
   if ((r = ensure_ring(ws, int64_t(1) << kRingMaxLg))) return r;
 
+  const int64_t brun = (int64_t)tuning(dtype).batched_run * mm::kTileOut;
   auto enqueue = [&]() -> hipError_t {
     int64_t* pre_tile = ws->pre;
     int64_t* pre_chunk = ws->pre + (S + 1);
     hipError_t e = mm::launch_batched_setup(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min,
-                                            ws->descs, pre_tile, pre_chunk, st);
+                                            ws->descs, pre_tile, pre_chunk, st, brun);
     if (e != hipSuccess) return e;
     JobArgs a;
     a.mode = 1;
     a.descs = ws->descs;
     a.S = S;
     a.pre = pre_tile;
-    a.run = mm::kRunBatched;
+    a.run = brun;
     e = mm::launch_1d(dtype, mm::kStratTile, a, mm::grid_cap(dtype, mm::kStratTile), st);
     if (e != hipSuccess) return e;
     a.pre = pre_chunk;
@@ -469,7 +490,7 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
     return ok();
   }
   // replay a captured graph of the three launches when the same call repeats
-  GraphKey key(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min);
+  GraphKey key(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min, brun);
   auto it = ws->graphs.find(key);
   if (it == ws->graphs.end()) {
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -606,7 +627,7 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   const int strat = plan_strategy(dtype, cols, w_cols);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
-    a.run = mm::kRunBatched;
+    a.run = (int64_t)tuning(dtype).batched_run * mm::kTileOut;
     a.tpr = mm::run_count(cols, w_cols, a.run);
     a.ntiles = a.tpr * rows;
     e = mm::launch_1d(dtype, mm::kStratTile, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratTile)), st);
@@ -717,6 +738,135 @@ int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int
     return r;
   return maxmin_filter_2d(dtype, mid, r1, c1, c1, w_rows, w_cols, open ? d_out : nullptr, open ? nullptr : d_out,
                           ld_out, stream);
+}
+
+// Autotuner: measure each launch parameter of the planner (Tuning) on this
+// device for `dtype`, one knob at a time with the others at their best so
+// far, and keep the fastest (a change needs more than 3% to count).  Inputs
+// are a constant-filled series of n elements (selection time does not
+// depend on the values); each candidate is the best of five timed launches
+// after one warm-up.
+int maxmin_autotune(int dtype, int64_t n, void* stream) {
+  const size_t s = dsize(dtype);
+  if (!s) return fail(MAXMIN_EINVAL, "maxmin_autotune: unknown dtype %d", dtype);
+  if (n == 0) n = int64_t(1) << 26;
+  if (n < (int64_t(1) << 20)) return fail(MAXMIN_EINVAL, "maxmin_autotune: n=%lld < 2^20", (long long)n);
+  hipStream_t st = (hipStream_t)stream;
+  if (capturing(st)) return fail(MAXMIN_EBUSY, "maxmin_autotune: the stream is being captured");
+  const int S = 64;
+  void *in = nullptr, *mx = nullptr, *mn = nullptr;
+  int64_t* arr = nullptr;  // in_offsets [S+1], windows [S], out_offsets [S+1]
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const Tuning before = tuning(dtype);
+  int r = MAXMIN_OK;
+  auto cleanup = [&]() {
+    if (st) hipStreamSynchronize(st);
+    else hipDeviceSynchronize();
+    if (in) hipFree(in);
+    if (mx) hipFree(mx);
+    if (mn) hipFree(mn);
+    if (arr) hipFree(arr);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (hipMalloc(&in, (size_t)n * s) != hipSuccess || hipMalloc(&mx, (size_t)n * s) != hipSuccess ||
+      hipMalloc(&mn, (size_t)n * s) != hipSuccess || hipMalloc((void**)&arr, (size_t)(3 * S + 2) * 8) != hipSuccess) {
+    cleanup();
+    return fail(MAXMIN_ENOMEM, "maxmin_autotune: cannot allocate %lld elements", (long long)n);
+  }
+  std::vector<int64_t> h(3 * S + 2);
+  const int64_t len = n / S, wb = 256;
+  for (int k = 0; k <= S; ++k) h[k] = k * len;
+  for (int k = 0; k < S; ++k) h[S + 1 + k] = wb;
+  for (int k = 0; k <= S; ++k) h[2 * S + 1 + k] = k * (len - wb + 1);
+  hipError_t e = hipMemsetAsync(in, 0x3c, (size_t)n * s, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(arr, h.data(), h.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "maxmin_autotune");
+  }
+  auto set = [&](const Tuning& t) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[dtype] = t;
+  };
+  auto time_ms = [&](const std::function<int()>& launch) -> float {
+    if ((r = launch())) return 0.f;
+    float best = 1e30f;
+    for (int k = 0; k < 5; ++k) {
+      hipEventRecord(e0, st);
+      if ((r = launch())) return 0.f;
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
+    }
+    return best;
+  };
+  Tuning best = before;
+  // a candidate replaces the current value only if it is more than 3%
+  // faster: run-to-run noise must not move the table
+  auto pick = [&](int Tuning::*field, std::initializer_list<int> cands, const std::function<int()>& launch) {
+    const int cur = best.*field;
+    float bt = time_ms(launch);
+    if (r) return;
+    int bv = cur;
+    for (int v : cands) {
+      if (v == cur) continue;
+      Tuning t = best;
+      t.*field = v;
+      set(t);
+      const float ms = time_ms(launch);
+      if (r) return;
+      if (ms < 0.97f * bt) {
+        bt = ms;
+        bv = v;
+      }
+    }
+    best.*field = bv;
+    set(best);
+  };
+  auto filt = [&](int64_t w) {
+    return std::function<int()>([=]() { return maxmin_filter(dtype, in, n, w, mx, mn, stream); });
+  };
+  pick(&Tuning::tile_run, {8, 16, 32, 64}, filt(256));
+  if (!r) pick(&Tuning::ranges_one, {0, 8, 16, 32}, filt(4096));
+  if (!r && n >= 4 * 65536) pick(&Tuning::long_strategy, {MAXMIN_STRATEGY_CHUNK, MAXMIN_STRATEGY_RUN}, filt(65536));
+  if (!r && n >= 4 * 65536 && best.long_strategy == MAXMIN_STRATEGY_CHUNK)
+    pick(&Tuning::ranges_long, {0, 16}, filt(65536));
+  if (!r)
+    pick(&Tuning::batched_run, {8, 16, 32}, std::function<int()>([=]() {
+           return maxmin_filter_batched(dtype, in, arr, arr + S + 1, arr + 2 * S + 1, S, mx, mn, stream);
+         }));
+  const int rr = r;
+  cleanup();
+  if (rr) {
+    set(before);
+    return rr;
+  }
+  best.tuned = 1;
+  set(best);
+  {
+    // graphs captured for the temporary buffers are of no further use
+    Workspace* ws = nullptr;
+    if (get_ws(st, &ws) == MAXMIN_OK) drop_graphs(ws);
+  }
+  return ok();
+}
+
+int maxmin_tuning(int dtype, int64_t* out6) {
+  if (!dsize(dtype)) return fail(MAXMIN_EINVAL, "maxmin_tuning: unknown dtype %d", dtype);
+  if (!out6) return fail(MAXMIN_EINVAL, "maxmin_tuning: null pointer");
+  const Tuning t = tuning(dtype);
+  out6[0] = t.tile_run;
+  out6[1] = t.batched_run;
+  out6[2] = t.ranges_one;
+  out6[3] = t.ranges_long;
+  out6[4] = t.long_strategy;
+  out6[5] = t.tuned;
+  return ok();
 }
 
 // Synchronise `stream` and report whether any look-back wait on it gave up.

@@ -1437,12 +1437,12 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
 
 hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
                                 const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
-                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st) {
+                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st, int64_t run) {
   return dispatch(dtype, [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
     const int g = (int)std::min<int64_t>((S + 255) / 256, 1024);
     hipLaunchKernelGGL(k_batched_count<T>, dim3(g), dim3(256), 0, st, (const T*)d_in, in_off, wins, out_off, S,
-                       (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk, (int64_t)kRunBatched);
+                       (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk, run);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batched_scan, dim3(1), dim3(1024), 0, st, S, pre_tile, pre_chunk);

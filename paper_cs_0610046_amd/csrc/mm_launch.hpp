@@ -48,12 +48,13 @@ __host__ __device__ inline int64_t run_count(int64_t n, int64_t w, int64_t run) 
   return no > 0 ? (no + run - 1) / run : 0;
 }
 // Run length for a single series on `grid` workgroups: about one run per
-// workgroup, a multiple of the sub-tile, at most kTileRunMax.
-inline int64_t run_length(int64_t nout, int64_t grid) {
+// workgroup, a multiple of the sub-tile, at most `cap` (kTileRunMax unless
+// the autotuner chose another).
+inline int64_t run_length(int64_t nout, int64_t grid, int64_t cap = kTileRunMax) {
   int64_t r = (nout + grid - 1) / grid;
   r = (r + kTileOut - 1) / kTileOut * kTileOut;
   r = r < kTileOut ? kTileOut : r;
-  return r > kTileRunMax ? kTileRunMax : r;
+  return r > cap ? cap : r;
 }
 // Number of chunk tiles covering [0, n) for window w (0 if n < w: no output).
 __host__ __device__ inline int64_t chunk_count(int64_t n, int64_t w) {
@@ -108,7 +109,7 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
 // and the per-strategy tile prefix sums pre_tile/pre_chunk (S+1 each).
 hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
                                 const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
-                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st);
+                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st, int64_t run = kRunBatched);
 
 // A stream push that completes no window: new carry = last min(n, w-1)
 // samples of (a[0..na) ++ b).

@@ -75,6 +75,15 @@ def test_argument_errors_without_gpu(lib):
     assert lib.maxmin_stream_samples(None) == -1
 
 
+def test_tuning_table_and_autotune_arguments(lib):
+    t = binding.maxmin_tuning(np.float32)
+    assert t == {"tile_run_subtiles": 16, "batched_run_subtiles": 16, "chunk_ranges_one_chunk": 16,
+                 "chunk_ranges_long": 0, "long_window_strategy": "chunk", "measured": False}
+    assert lib.maxmin_autotune(9, 0, None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_autotune(0, 1000, None) == binding.MAXMIN_EINVAL  # below 2^20, checked before any device call
+    assert lib.maxmin_tuning(9, None) == binding.MAXMIN_EINVAL
+
+
 def test_out_offsets_matches_oracle(lib):
     rng = np.random.default_rng(3)
     lens = rng.integers(0, 50, 200)
