@@ -384,11 +384,25 @@ int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s) || !aligned(d_argmax, 8) || !aligned(d_argmin, 8))
     return fail(MAXMIN_EINVAL, "maxmin_argfilter: pointer not aligned to the element size");
   hipStream_t st = (hipStream_t)stream;
-  // windows: w, ceil(w/2), ... down to the first one the tile kernel takes
+  // windows: w, then ceil(w/F), ... down to the first one the tile kernel
+  // takes, with the fewest steps of fan-in F <= 16 (each step reads F
+  // shorter windows per output)
+  int L = 0;
+  for (int64_t p = w; p > mm::kTileMaxW; p = (p + 15) / 16) ++L;
+  int F = 1;
+  if (L > 0) {
+    // the smallest F whose L-th power reaches w / kTileMaxW
+    F = 2;
+    for (;;) {
+      int64_t p = w;
+      for (int l = 0; l < L; ++l) p = (p + F - 1) / F;
+      if (p <= mm::kTileMaxW) break;
+      ++F;
+    }
+  }
   std::vector<int64_t> chain{w};
-  while (chain.back() > mm::kTileMaxW) chain.push_back((chain.back() + 1) / 2);
+  for (int l = 0; l < L; ++l) chain.push_back((chain.back() + F - 1) / F);
   std::reverse(chain.begin(), chain.end());
-  const int L = (int)chain.size() - 1;  // doubling steps
   // level buffers: values (max, min) and locations (max, min), two sets
   char* set[2] = {nullptr, nullptr};
   const size_t set_bytes = (size_t)n * (2 * s + 2 * sizeof(int64_t));
@@ -423,10 +437,11 @@ int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_
   for (int l = 1; l <= L; ++l) {
     const int src = (l - 1) & 1, dst = l & 1;
     const bool last = l == L;
-    e = mm::launch_arg_combine(dtype, vx(src), vn(src), ix(src), in(src), chain[l] - chain[l - 1], n - chain[l] + 1,
-                               last ? d_max : vx(dst), last ? d_min : vn(dst), last ? d_argmax : ix(dst),
+    const int64_t q = chain[l - 1], p = chain[l];
+    e = mm::launch_arg_combine(dtype, vx(src), vn(src), ix(src), in(src), q, p, (int)((p + q - 1) / q),
+                               n - p + 1, last ? d_max : vx(dst), last ? d_min : vn(dst), last ? d_argmax : ix(dst),
                                last ? d_argmin : in(dst), st);
-    if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter (doubling)");
+    if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter (combine)");
   }
   return ok();
 }

@@ -859,27 +859,41 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
 }
 
 // ================================================ arg filter, long windows
-// A window [j, j+p) is the union of [j, j+q) and [j+p-q, j+p) when
-// p <= 2q, so its leftmost max (min) is the leftmost of the two shorter
-// windows' results: one doubling step maps the (value, location) outputs of
-// window q to those of window p.  Used for windows longer than the tile
-// kernel takes (w > kTileMaxW), starting from a tile-kernel pass.
+// A window [j, j+p) is the union of the F windows of a shorter length q
+// starting at j, j+q, ..., j+(F-2)q and j+p-q when p <= F q (they overlap
+// at the end), so its leftmost max (min) is the leftmost of their (value,
+// location) results.  One step maps window q's outputs to window p's; long
+// windows start from a tile-kernel pass (w > kTileMaxW).  The F reads of an
+// output hit consecutive addresses across a wavefront and mostly come from
+// cache.
 template <class T>
 __global__ __launch_bounds__(256) void k_argcombine(const T* __restrict__ vx, const T* __restrict__ vn,
                                                     const int64_t* __restrict__ ix, const int64_t* __restrict__ in_,
-                                                    int64_t d, int64_t nout, T* __restrict__ ox, T* __restrict__ on,
-                                                    int64_t* __restrict__ jx, int64_t* __restrict__ jn) {
+                                                    int64_t q, int64_t p, int F, int64_t nout, T* __restrict__ ox,
+                                                    T* __restrict__ on, int64_t* __restrict__ jx,
+                                                    int64_t* __restrict__ jn) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nout; j += stride) {
-    const T a = gload(vx + j), b = gload(vx + j + d), c = gload(vn + j), e = gload(vn + j + d);
-    const int64_t la = gload(ix + j), lb = gload(ix + j + d), lc = gload(in_ + j), le = gload(in_ + j + d);
-    // equal values: the smaller location wins (both lie in the window)
-    const bool ta = a > b || (a == b && la <= lb);
-    const bool tc = c < e || (c == e && lc <= le);
-    gstore(ox + j, ta ? a : b);
-    gstore(jx + j, ta ? la : lb);
-    gstore(on + j, tc ? c : e);
-    gstore(jn + j, tc ? lc : le);
+    T bx = gload(vx + j), bn = gload(vn + j);
+    int64_t lx = gload(ix + j), ln = gload(in_ + j);
+    for (int f = 1; f < F; ++f) {
+      const int64_t o = j + min((int64_t)f * q, p - q);
+      const T a = gload(vx + o), c = gload(vn + o);
+      const int64_t la = gload(ix + o), lc = gload(in_ + o);
+      // equal values: the smaller location wins (all lie in the window)
+      if (a > bx || (a == bx && la < lx)) {
+        bx = a;
+        lx = la;
+      }
+      if (c < bn || (c == bn && lc < ln)) {
+        bn = c;
+        ln = lc;
+      }
+    }
+    gstore(ox + j, bx);
+    gstore(jx + j, lx);
+    gstore(on + j, bn);
+    gstore(jn + j, ln);
   }
 }
 
@@ -1451,13 +1465,14 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
 }
 
 hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,
-                              int64_t d, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn, hipStream_t st) {
+                              int64_t q, int64_t p, int F, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn,
+                              hipStream_t st) {
   if (nout <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((nout + 255) / 256, (int64_t)cu_count() * 16);
-  return dispatch(dtype, [&](auto* p) {
-    using T = std::remove_pointer_t<decltype(p)>;
-    hipLaunchKernelGGL(k_argcombine<T>, dim3(grid), dim3(256), 0, st, (const T*)vx, (const T*)vn, ix, in_, d, nout,
-                       (T*)ox, (T*)on, jx, jn);
+  return dispatch(dtype, [&](auto* ptr) {
+    using T = std::remove_pointer_t<decltype(ptr)>;
+    hipLaunchKernelGGL(k_argcombine<T>, dim3(grid), dim3(256), 0, st, (const T*)vx, (const T*)vn, ix, in_, q, p, F,
+                       nout, (T*)ox, (T*)on, jx, jn);
     return hipGetLastError();
   });
 }

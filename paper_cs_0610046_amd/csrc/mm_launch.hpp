@@ -120,10 +120,11 @@ hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st);
 hipError_t launch_env_ends(int dtype, const void* a, int64_t n, int64_t r, void* up, void* lo, hipStream_t st);
 hipError_t launch_env_batched(int dtype, const void* in, const int64_t* off, const int64_t* radii, int64_t S,
                               int64_t* wins, int64_t* oo, bool setup, void* up, void* lo, hipStream_t st);
-// One doubling step of the arg filter (see k_argcombine): outputs j < nout
-// from inputs j and j + d of the shorter window's value/location arrays.
+// One step of the arg filter's long-window path (see k_argcombine): window
+// p's outputs j < nout from F reads of window q's value/location arrays.
 hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,
-                              int64_t d, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn, hipStream_t st);
+                              int64_t q, int64_t p, int F, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn,
+                              hipStream_t st);
 
 size_t series_bytes();
 
