@@ -139,6 +139,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <class T> struct TileLds {
   T pm[lds_len<T>(2 * kTileOut)];  // PRE (max) ring, indexed by position mod 2*kTileOut
   T pn[lds_len<T>(2 * kTileOut)];  // PRE (min) ring
+  T wt[4][kTileThreads / 64];      // wavefront totals (blocks of two wavefronts)
 };
 
 // Series and outputs need not be 16-byte aligned (a packed batch puts
@@ -297,8 +298,9 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   const int w = (int)s.w;
   const int lgB = 31 - __builtin_clz((unsigned)min(w, kTileMaxBlock));
   const int B = 1 << lgB;
-  const int m = B > V ? B / V : 1;  // lanes per block
-  const int lig = tid & (m - 1);
+  const int m = B > V ? B / V : 1;  // lanes per block (128: two wavefronts)
+  const int mw = m < 64 ? m : 64;     // lanes per block within one wavefront
+  const int lig = tid & (mw - 1);
   const int64_t nout = s.n - s.w + 1;
   const int64_t lim = min(s.n, R1 + (int64_t)w - 1);  // inputs used: [R0, lim)
   const int nsub = (int)((R1 - 1 - R0) / TT) + 2;     // sub-tiles P_0 .. P_{nsub-1}
@@ -334,50 +336,44 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     const bool live = R0 + (int64_t)k * TT < lim;
     E ux[V], un[V];
     if (live) {
-      // PRE of P_k into the ring
-      {
-        E px[V], pn[V];
-        px[0] = elem(cur[0], pr0, et);
-        pn[0] = px[0];
+      // PRE of P_k: within the thread, then across the lanes of its block
+      E px[V], pn[V];
+      px[0] = elem(cur[0], pr0, et);
+      pn[0] = px[0];
 #pragma unroll
-        for (int i = 1; i < V; ++i) {
-          const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
-          const E c = elem(cur[i], pr0 + i, et);
-          px[i] = start ? c : hmax(px[i - 1], c);
-          pn[i] = start ? c : hmin(pn[i - 1], c);
-        }
-        if (m > 1) {
-          // a block spans m aligned lanes: exclusive scan of the lane totals
-          E ix = px[V - 1], in = pn[V - 1];
-          E cx, cn;
-          if constexpr (!ARG) {
-            seg_prefix2<T, true>(ix, in, m, lig);
-            cx = dpp<0x138>(Lim<T>::lo(), ix);  // wave_shr:1 (read only where lig > 0)
-            cn = dpp<0x138>(Lim<T>::hi(), in);
-          } else {
-            for (int d = 1; d < m; d <<= 1) {
-              const E a = shup(ix, d, m), b = shup(in, d, m);
-              if (lig >= d) {
-                ix = hmax(ix, a);
-                in = hmin(in, b);
-              }
-            }
-            cx = shup(ix, 1, m);
-            cn = shup(in, 1, m);
-          }
-          if (lig > 0) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-              px[i] = hmax(px[i], cx);
-              pn[i] = hmin(pn[i], cn);
+      for (int i = 1; i < V; ++i) {
+        const bool start = ((pr0 + i) & (B - 1)) == 0;  // a block begins here
+        const E c = elem(cur[i], pr0 + i, et);
+        px[i] = start ? c : hmax(px[i - 1], c);
+        pn[i] = start ? c : hmin(pn[i - 1], c);
+      }
+      if (m > 1) {
+        // a block spans mw aligned lanes of the wavefront (all of it, and
+        // then the next wavefront too, when m > 64): exclusive scan of the
+        // lane totals
+        E ix = px[V - 1], in = pn[V - 1];
+        E cx, cn;
+        if constexpr (!ARG) {
+          seg_prefix2<T, true>(ix, in, mw, lig);
+          cx = dpp<0x138>(Lim<T>::lo(), ix);  // wave_shr:1 (read only where lig > 0)
+          cn = dpp<0x138>(Lim<T>::hi(), in);
+        } else {
+          for (int d = 1; d < mw; d <<= 1) {
+            const E a = shup(ix, d, mw), b = shup(in, d, mw);
+            if (lig >= d) {
+              ix = hmax(ix, a);
+              in = hmin(in, b);
             }
           }
+          cx = shup(ix, 1, mw);
+          cn = shup(in, 1, mw);
         }
-        const int slot = pr0 & (RING - 1);
+        if (lig > 0) {
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          sm.pm[lds_idx<E>(slot + i)] = px[i];
-          sm.pn[lds_idx<E>(slot + i)] = pn[i];
+          for (int i = 0; i < V; ++i) {
+            px[i] = hmax(px[i], cx);
+            pn[i] = hmin(pn[i], cn);
+          }
         }
       }
       // SUF of P_k, kept for the next sub-tile's outputs
@@ -394,27 +390,62 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         E jx = ux[0], jn = un[0];
         E cx, cn;
         if constexpr (!ARG) {
-          seg_suffix2<T, true>(jx, jn, m, lig);
-          cx = dpp<0x130>(Lim<T>::lo(), jx);  // wave_shl:1 (read only where lig < m-1)
+          seg_suffix2<T, true>(jx, jn, mw, lig);
+          cx = dpp<0x130>(Lim<T>::lo(), jx);  // wave_shl:1 (read only where lig < mw-1)
           cn = dpp<0x130>(Lim<T>::hi(), jn);
         } else {
-          for (int d = 1; d < m; d <<= 1) {
-            const E a = shdn(jx, d, m), b = shdn(jn, d, m);
-            if (lig + d < m) {
+          for (int d = 1; d < mw; d <<= 1) {
+            const E a = shdn(jx, d, mw), b = shdn(jn, d, mw);
+            if (lig + d < mw) {
               jx = hmax(jx, a);
               jn = hmin(jn, b);
             }
           }
-          cx = shdn(jx, 1, m);
-          cn = shdn(jn, 1, m);
+          cx = shdn(jx, 1, mw);
+          cn = shdn(jn, 1, mw);
         }
-        if (lig < m - 1) {
+        if (lig < mw - 1) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
             ux[i] = hmax(ux[i], cx);
             un[i] = hmin(un[i], cn);
           }
         }
+      }
+      if (m > 64) {
+        // blocks of two wavefronts: the odd one takes the even one's total
+        // into its PRE, the even one the odd one's into its SUF
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 63) {
+          sm.wt[0][wv] = px[V - 1];
+          sm.wt[1][wv] = pn[V - 1];
+        }
+        if (lane == 0) {
+          sm.wt[2][wv] = ux[0];
+          sm.wt[3][wv] = un[0];
+        }
+        __syncthreads();
+        if (wv & 1) {
+          const E cx = sm.wt[0][wv - 1], cn = sm.wt[1][wv - 1];
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            px[i] = hmax(px[i], cx);
+            pn[i] = hmin(pn[i], cn);
+          }
+        } else {
+          const E cx = sm.wt[2][wv + 1], cn = sm.wt[3][wv + 1];
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            ux[i] = hmax(ux[i], cx);
+            un[i] = hmin(un[i], cn);
+          }
+        }
+      }
+      const int slot = pr0 & (RING - 1);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        sm.pm[lds_idx<E>(slot + i)] = px[i];
+        sm.pn[lds_idx<E>(slot + i)] = pn[i];
       }
       __syncthreads();  // PRE of P_k visible
     }

@@ -13,8 +13,8 @@ namespace mm {
 constexpr int kTileThreads = 256;
 constexpr int kTileV = 8;                                   // positions per thread
 constexpr int kTileOut = kTileThreads * kTileV;             // 2048 positions per sub-tile
-constexpr int kTileMaxBlock = kTileV * 64;                  // largest block: 64 lanes
-constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 1024: w <= 2 * block size
+constexpr int kTileMaxBlock = kTileV * 128;                 // largest block: 128 lanes, two wavefronts
+constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 2048: w <= 2 * block size, w - 1 <= sub-tile
 // Longest run: on MI355X (n = 2^28 and 2^30 float32) runs of 16 sub-tiles,
 // dealt round robin, beat one long run per workgroup by 5-6%.
 constexpr int64_t kTileRunMax = 16 * kTileOut;

@@ -67,7 +67,8 @@ def test_plain_all_windows(dt):
 def test_forced_strategies_agree(strategy):
     rng = synth.rng_for("tests", 101)
     for dt in DTS:
-        for w in [1, 2, 5, 33, 100, 512, 700, 1024] + ([1025, 3000, 4097, 9000] if strategy != mm.STRATEGY_TILE else []):
+        for w in [1, 2, 5, 33, 100, 512, 700, 1024, 1025, 1500, 2048] + \
+                 ([2049, 3000, 4097, 9000] if strategy != mm.STRATEGY_TILE else []):
             n = int(rng.integers(w, 3 * 2048 + w))
             a = gen(n, dt, rng, "walk" if w % 2 else "ties")
             note("forced=%d dt=%s n=%d w=%d" % (strategy, np.dtype(dt).name, n, w))
