@@ -295,7 +295,7 @@ def run_extras(torch, mm, synth, dev, stream):
         ab = xa.numel() * 4 + outs[0].numel() * (2 * 4 + 2 * 8)
         res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(xa.numel() / (ms * 1e-3) / 1e9, 2),
                        "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
-                       "path": "tile with locations" if w <= 1024 else "tile + combine steps"}
+                       "path": "tile with locations" if w <= 2048 else "tile + combine steps"}
         del outs
     out["argfilter"] = {"workload": "n=2^28 float32 walk; max, min and their leftmost int64 locations "
                                     "(algorithmic bytes: 4 read + 24 written per window)", "per_window": res}

@@ -68,7 +68,7 @@ struct Tuning {
   int batched_run = 16;  // sub-tiles per run, batched and 2-D row launches
   int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096)
   int ranges_long = 0;   // chunk ticket ranges, longer windows
-  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 1024: chunk or run
+  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 2048: chunk or run
   int tuned = 0;
 };
 std::mutex g_tune_mu;
@@ -97,7 +97,7 @@ int64_t run_chunks_per_run(int dt, int64_t n, int64_t w) {
   const int64_t cap = mm::grid_cap(dt, mm::kStratRun);
   return std::max<int64_t>(1, (nch + cap - 1) / cap);
 }
-// Planner: streaming tiles for w <= 1024, chunks with cross-workgroup
+// Planner: streaming tiles for w <= 2048, chunks with cross-workgroup
 // look-back above.  Chunk runs are used only when forced: on MI355X with
 // n = 2^28 float32 they ran slower than look-back chunks at w = 4096 and 8192
 // (1.46 ms against 0.83 and 0.88 ms).
