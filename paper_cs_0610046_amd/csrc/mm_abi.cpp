@@ -66,9 +66,9 @@ std::atomic<int> g_force{0};
 struct Tuning {
   int tile_run = 16;     // sub-tiles per run, single-series tile launches
   int batched_run = 16;  // sub-tiles per run, batched and 2-D row launches
-  int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096)
+  int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096; chunk strategy forced)
   int ranges_long = 0;   // chunk ticket ranges, longer windows
-  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 2048: chunk or run
+  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 4096: chunk or run
   int tuned = 0;
 };
 std::mutex g_tune_mu;
@@ -97,7 +97,7 @@ int64_t run_chunks_per_run(int dt, int64_t n, int64_t w) {
   const int64_t cap = mm::grid_cap(dt, mm::kStratRun);
   return std::max<int64_t>(1, (nch + cap - 1) / cap);
 }
-// Planner: streaming tiles for w <= 2048, chunks with cross-workgroup
+// Planner: streaming tiles for w <= 4096, chunks with cross-workgroup
 // look-back above.  Chunk runs are used only when forced: on MI355X with
 // n = 2^28 float32 they ran slower than look-back chunks at w = 4096 and 8192
 // (1.46 ms against 0.83 and 0.88 ms).
@@ -108,10 +108,13 @@ int plan_strategy(int dt, int64_t n, int64_t w) {
   const bool run_ok = (w + mm::kCrMax - 1) / mm::kCrMax <= mm::kCrRing;
   if (f == MAXMIN_STRATEGY_CHUNK) return MAXMIN_STRATEGY_CHUNK;
   if (f == MAXMIN_STRATEGY_RUN && run_ok) return MAXMIN_STRATEGY_RUN;
-  if (w <= mm::kTileMaxW) return MAXMIN_STRATEGY_TILE;
+  if (w <= mm::kTileMaxW2) return MAXMIN_STRATEGY_TILE;
   if (!f && run_ok && tuning(dt).long_strategy == MAXMIN_STRATEGY_RUN) return MAXMIN_STRATEGY_RUN;
   return MAXMIN_STRATEGY_CHUNK;
 }
+
+// Which tile kernel a single series or a row pass of window w runs.
+int tile_kind(int64_t w) { return w <= mm::kTileMaxW ? mm::kStratTile : mm::kStratTile2; }
 
 // ------------------------------------------------------------ workspaces
 typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*, int64_t> GraphKey;
@@ -270,15 +273,20 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
   const int strat = plan_strategy(dt, a.n, a.w);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
-    const int cap = mm::grid_cap(dt, mm::kStratTile);
-    a.run = mm::run_length(a.n - a.w + 1, cap, (int64_t)tuning(dt).tile_run * mm::kTileOut);
+    const int ks = tile_kind(a.w);
+    const int cap = mm::grid_cap(dt, ks);
+    // a run re-reads the w-1 inputs after it: runs 4x longer for windows
+    // over two sub-tiles (MI355X, n = 2^28 float32, w = 2049..4096: 64
+    // sub-tiles 0.71-0.73 ms, 32: 0.72-0.73, 16: 0.74-0.75)
+    const int64_t rmax = (int64_t)tuning(dt).tile_run * (ks == mm::kStratTile2 ? 4 : 1) * mm::kTileOut;
+    a.run = mm::run_length(a.n - a.w + 1, cap, rmax);
     if (const char* e = getenv("MAXMIN_TILE_RUN")) {
       const int64_t r = atoll(e) / mm::kTileOut * mm::kTileOut;
       if (r > 0 && r < a.run) a.run = r;
     }
     a.ntiles = mm::run_count(a.n, a.w, a.run);
     const int grid = (int)std::min<int64_t>(a.ntiles, cap);
-    e = mm::launch_1d(dt, mm::kStratTile, a, grid, st);
+    e = mm::launch_1d(dt, ks, a, grid, st);
   } else if (strat == MAXMIN_STRATEGY_RUN) {
     a.run = run_chunks_per_run(dt, a.n, a.w);
     a.ntiles = (mm::crun_chunks(a.n, a.w) + a.run - 1) / a.run;
@@ -388,15 +396,15 @@ int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_
   // takes, with the fewest steps of fan-in F <= 16 (each step reads F
   // shorter windows per output)
   int L = 0;
-  for (int64_t p = w; p > mm::kTileMaxW; p = (p + 15) / 16) ++L;
+  for (int64_t p = w; p > mm::kTileMaxW2; p = (p + 15) / 16) ++L;
   int F = 1;
   if (L > 0) {
-    // the smallest F whose L-th power reaches w / kTileMaxW
+    // the smallest F whose L-th power reaches w / kTileMaxW2
     F = 2;
     for (;;) {
       int64_t p = w;
       for (int l = 0; l < L; ++l) p = (p + F - 1) / F;
-      if (p <= mm::kTileMaxW) break;
+      if (p <= mm::kTileMaxW2) break;
       ++F;
     }
   }
@@ -429,10 +437,11 @@ int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_
   a.omin = L ? vn(0) : d_min;
   a.amax = L ? ix(0) : d_argmax;
   a.amin = L ? in(0) : d_argmin;
-  const int cap = mm::grid_cap(dtype, mm::kStratArg);
-  a.run = mm::run_length(n - a.w + 1, cap);
+  const int ks = a.w <= mm::kTileMaxW ? mm::kStratArg : mm::kStratArg2;
+  const int cap = mm::grid_cap(dtype, ks);
+  a.run = mm::run_length(n - a.w + 1, cap, (ks == mm::kStratArg2 ? 4 : 1) * mm::kTileRunMax);
   a.ntiles = mm::run_count(n, a.w, a.run);
-  hipError_t e = mm::launch_1d(dtype, mm::kStratArg, a, (int)std::min<int64_t>(a.ntiles, cap), st);
+  hipError_t e = mm::launch_1d(dtype, ks, a, (int)std::min<int64_t>(a.ntiles, cap), st);
   if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter");
   for (int l = 1; l <= L; ++l) {
     const int src = (l - 1) & 1, dst = l & 1;
@@ -645,7 +654,8 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
     a.run = (int64_t)tuning(dtype).batched_run * mm::kTileOut;
     a.tpr = mm::run_count(cols, w_cols, a.run);
     a.ntiles = a.tpr * rows;
-    e = mm::launch_1d(dtype, mm::kStratTile, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratTile)), st);
+    const int ks = tile_kind(w_cols);
+    e = mm::launch_1d(dtype, ks, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, ks)), st);
   } else if (strat == MAXMIN_STRATEGY_RUN) {
     a.run = mm::crun_chunks(cols, w_cols);  // one run per row
     a.tpr = 1;
@@ -847,7 +857,10 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
     return std::function<int()>([=]() { return maxmin_filter(dtype, in, n, w, mx, mn, stream); });
   };
   pick(&Tuning::tile_run, {8, 16, 32, 64}, filt(256));
-  if (!r) pick(&Tuning::ranges_one, {0, 8, 16, 32}, filt(4096));
+  // one-chunk windows run the tile kernel unless the chunk strategy is
+  // forced: only then are their ticket ranges worth measuring
+  if (!r && plan_strategy(dtype, n, 4096) == MAXMIN_STRATEGY_CHUNK)
+    pick(&Tuning::ranges_one, {0, 8, 16, 32}, filt(4096));
   if (!r && n >= 4 * 65536) pick(&Tuning::long_strategy, {MAXMIN_STRATEGY_CHUNK, MAXMIN_STRATEGY_RUN}, filt(65536));
   if (!r && n >= 4 * 65536 && best.long_strategy == MAXMIN_STRATEGY_CHUNK)
     pick(&Tuning::ranges_long, {0, 16}, filt(65536));

@@ -139,7 +139,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <class T> struct TileLds {
   T pm[lds_len<T>(2 * kTileOut)];  // PRE (max) ring, indexed by position mod 2*kTileOut
   T pn[lds_len<T>(2 * kTileOut)];  // PRE (min) ring
-  T wt[4][kTileThreads / 64];      // wavefront totals (blocks of two wavefronts)
+  T wt[4][kTileThreads / 64];      // wavefront totals (blocks of two or four wavefronts)
 };
 
 // Series and outputs need not be 16-byte aligned (a packed batch puts
@@ -287,7 +287,12 @@ __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_
 // ARG: also the leftmost location of every window's max and min (values
 // travel with their location relative to R0; outputs amax/amin get R0 +
 // location, the position in the series).
-template <class T, bool ARG>
+// LAG: sub-tiles between a window's first and last element.  LAG 1 (w <=
+// 2048): blocks up to 1024, the windows starting in P_{k-1} are emitted
+// once P_k is scanned.  LAG 2 (2048 < w <= 4096): blocks of one whole
+// sub-tile (four wavefronts), the windows starting in P_{k-2} are emitted
+// once P_k is scanned, so two sub-tiles of SUF stay in registers.
+template <class T, bool ARG, int LAG>
 __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t R1,
                                          TileLds<typename ElemOf<T, ARG>::type>& sm, int64_t* amax,
                                          int64_t* amin) {
@@ -296,14 +301,15 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   constexpr int NT = kTileThreads, V = kTileV, TT = kTileOut, RING = 2 * kTileOut;
   const int tid = threadIdx.x;
   const int w = (int)s.w;
-  const int lgB = 31 - __builtin_clz((unsigned)min(w, kTileMaxBlock));
+  static_assert(LAG == 1 || LAG == 2, "emission lag of one or two sub-tiles");
+  const int lgB = 31 - __builtin_clz((unsigned)min(w, LAG == 1 ? kTileMaxBlock : TT));
   const int B = 1 << lgB;
-  const int m = B > V ? B / V : 1;  // lanes per block (128: two wavefronts)
+  const int m = B > V ? B / V : 1;  // lanes per block (128, 256: two, four wavefronts)
   const int mw = m < 64 ? m : 64;     // lanes per block within one wavefront
   const int lig = tid & (mw - 1);
   const int64_t nout = s.n - s.w + 1;
   const int64_t lim = min(s.n, R1 + (int64_t)w - 1);  // inputs used: [R0, lim)
-  const int nsub = (int)((R1 - 1 - R0) / TT) + 2;     // sub-tiles P_0 .. P_{nsub-1}
+  const int nsub = (int)((R1 - 1 - R0) / TT) + 1 + LAG;  // sub-tiles P_0 .. P_{nsub-1}
   // 16-byte loads when [R0, lim) lies in one source segment
   constexpr int EV = 16 / (int)sizeof(T);
   const T* vbase = nullptr;
@@ -319,6 +325,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
 
   T cur[V], nxt[V];
   E sx[V], sn[V];  // SUF of the previous sub-tile's positions
+  E tx[V], tn[V];  // LAG 2: SUF of the sub-tile before that
   run_load<T>(s, vbase, din, R0 + tid * V, lim, cur);
   for (int k = 0; k < nsub; ++k) {
     const int pr0 = k * TT + tid * V;  // position of cur[0], relative to R0
@@ -413,9 +420,10 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         }
       }
       if (m > 64) {
-        // blocks of two wavefronts: the odd one takes the even one's total
-        // into its PRE, the even one the odd one's into its SUF
-        const int lane = tid & 63, wv = tid >> 6;
+        // blocks of G = m/64 wavefronts: each takes the totals of the
+        // block's earlier wavefronts into its PRE and of its later ones
+        // into its SUF (wavefront-uniform branches)
+        const int lane = tid & 63, wv = tid >> 6, G = m >> 6, g0 = wv & ~(G - 1);
         if (lane == 63) {
           sm.wt[0][wv] = px[V - 1];
           sm.wt[1][wv] = pn[V - 1];
@@ -425,15 +433,24 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
           sm.wt[3][wv] = un[0];
         }
         __syncthreads();
-        if (wv & 1) {
-          const E cx = sm.wt[0][wv - 1], cn = sm.wt[1][wv - 1];
+        if (wv > g0) {
+          E cx = sm.wt[0][g0], cn = sm.wt[1][g0];
+          for (int o = g0 + 1; o < wv; ++o) {
+            cx = hmax(cx, sm.wt[0][o]);
+            cn = hmin(cn, sm.wt[1][o]);
+          }
 #pragma unroll
           for (int i = 0; i < V; ++i) {
             px[i] = hmax(px[i], cx);
             pn[i] = hmin(pn[i], cn);
           }
-        } else {
-          const E cx = sm.wt[2][wv + 1], cn = sm.wt[3][wv + 1];
+        }
+        if (wv < g0 + G - 1) {
+          E cx = sm.wt[2][g0 + G - 1], cn = sm.wt[3][g0 + G - 1];
+          for (int o = g0 + G - 2; o > wv; --o) {
+            cx = hmax(cx, sm.wt[2][o]);
+            cn = hmin(cn, sm.wt[3][o]);
+          }
 #pragma unroll
           for (int i = 0; i < V; ++i) {
             ux[i] = hmax(ux[i], cx);
@@ -449,16 +466,18 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       }
       __syncthreads();  // PRE of P_k visible
     }
-    if (k > 0) {
-      // windows starting in P_{k-1}: SUF (registers), PRE at the window end
-      // and the whole block strictly inside, if any (both from the ring)
-      const int qr0 = pr0 - TT;
+    if (k >= LAG) {
+      // windows starting in P_{k-LAG}: SUF (registers), PRE at the window
+      // end and the whole block strictly inside, if any (both from the ring;
+      // the ends lie in P_{k-1} or P_k)
+      const int qr0 = pr0 - LAG * TT;
       E ox[V], on[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const int q = qr0 + i, e = q + w - 1;
-        E rx = hmax(sx[i], sm.pm[lds_idx<E>(e & (RING - 1))]);
-        E rn = hmin(sn[i], sm.pn[lds_idx<E>(e & (RING - 1))]);
+        const E fx = LAG == 2 ? tx[i] : sx[i], fn = LAG == 2 ? tn[i] : sn[i];
+        E rx = hmax(fx, sm.pm[lds_idx<E>(e & (RING - 1))]);
+        E rn = hmin(fn, sm.pn[lds_idx<E>(e & (RING - 1))]);
         const int b1 = q >> lgB, b2 = e >> lgB;
         if (b2 >= b1 + 2) {
           const int mi = (((b1 + 2) << lgB) - 1) & (RING - 1);
@@ -488,6 +507,10 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
+      if constexpr (LAG == 2) {
+        tx[i] = sx[i];
+        tn[i] = sn[i];
+      }
       if (live) {
         sx[i] = ux[i];
         sn[i] = un[i];
@@ -500,7 +523,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
 
 // Persistent: static round-robin over runs (runs share no data beyond a
 // w-1 halo; on MI355X this beat the XCD-contiguous schedule by ~2%).
-template <int MODE, class T, bool ARG = false>
+template <int MODE, class T, bool ARG = false, int LAG = 1>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
   __shared__ TileLds<typename ElemOf<T, ARG>::type> sm;
   const int64_t nruns = job_tiles<MODE>(job);
@@ -509,7 +532,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
     const Series<T> s = job_series<MODE>(job, t, local, gbase);
     const int64_t nout = s.n - s.w + 1;
     const int64_t R0 = local * job.run;
-    run_body<T, ARG>(s, R0, min(nout, R0 + job.run), sm, job.amax, job.amin);
+    run_body<T, ARG, LAG>(s, R0, min(nout, R0 + job.run), sm, job.amax, job.amin);
   }
 }
 
@@ -1439,8 +1462,8 @@ template <class K> static int occupancy_grid(K kernel, int threads) {
 }
 
 int grid_cap(int dtype, int strategy) {
-  static int cap[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratArg) return 0;
+  static int cap[6][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratArg2) return 0;
   int& c = cap[strategy - 1][dtype];
   if (!c) {
     (void)dispatch(dtype, [&](auto* p) {
@@ -1448,6 +1471,8 @@ int grid_cap(int dtype, int strategy) {
       c = strategy == kStratTile    ? occupancy_grid(k_tile<kJobDescs, T>, kTileThreads)
           : strategy == kStratChunk ? occupancy_grid(k_chunk<kJobDescs, T>, kChunkThreads)
           : strategy == kStratArg   ? occupancy_grid(k_tile<kJobOne, T, true>, kTileThreads)
+          : strategy == kStratTile2 ? occupancy_grid(k_tile<kJobOne, T, false, 2>, kTileThreads)
+          : strategy == kStratArg2  ? occupancy_grid(k_tile<kJobOne, T, true, 2>, kTileThreads)
                                     : occupancy_grid(k_crun<kJobDescs, T>, kChunkThreads);
       return hipSuccess;
     });
@@ -1460,10 +1485,24 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
     using T = std::remove_pointer_t<decltype(p)>;
     const Job<T> j = make_job<T>(a);
     const dim3 g(grid);
-    if (strategy == kStratArg) {
+    if (strategy == kStratArg || strategy == kStratArg2) {
       if (a.mode != kJobOne || a.amax == nullptr || a.amin == nullptr) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_tile<kJobOne, T, true>), g, dim3(kTileThreads), 0, st, j);
+      if (strategy == kStratArg) {
+        if (a.w > kTileMaxW) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tile<kJobOne, T, true>), g, dim3(kTileThreads), 0, st, j);
+      } else {
+        if (a.w <= kTileMaxW || a.w > kTileMaxW2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tile<kJobOne, T, true, 2>), g, dim3(kTileThreads), 0, st, j);
+      }
+    } else if (strategy == kStratTile2) {
+      // the two-sub-tile emission lag needs every window to end past its
+      // own sub-tile and at most two sub-tiles on
+      if (a.w <= kTileMaxW || a.w > kTileMaxW2) return hipErrorInvalidValue;
+      if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T, false, 2>), g, dim3(kTileThreads), 0, st, j);
+      else if (a.mode == kJobRows) hipLaunchKernelGGL((k_tile<kJobRows, T, false, 2>), g, dim3(kTileThreads), 0, st, j);
+      else return hipErrorInvalidValue;
     } else if (strategy == kStratTile) {
+      if (a.mode != kJobDescs && a.w > kTileMaxW) return hipErrorInvalidValue;
       if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T>), g, dim3(kTileThreads), 0, st, j);
       else if (a.mode == kJobDescs) hipLaunchKernelGGL((k_tile<kJobDescs, T>), g, dim3(kTileThreads), 0, st, j);
       else hipLaunchKernelGGL((k_tile<kJobRows, T>), g, dim3(kTileThreads), 0, st, j);

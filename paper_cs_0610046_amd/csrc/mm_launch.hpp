@@ -15,6 +15,9 @@ constexpr int kTileV = 8;                                   // positions per thr
 constexpr int kTileOut = kTileThreads * kTileV;             // 2048 positions per sub-tile
 constexpr int kTileMaxBlock = kTileV * 128;                 // largest block: 128 lanes, two wavefronts
 constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 2048: w <= 2 * block size, w - 1 <= sub-tile
+// Second instantiation (kStratTile2, single series and rows): blocks of a
+// whole sub-tile, windows end at most two sub-tiles after they start.
+constexpr int64_t kTileMaxW2 = 2 * kTileOut;                // 4096
 // Longest run: on MI355X (n = 2^28 and 2^30 float32) runs of 16 sub-tiles,
 // dealt round robin, beat one long run per workgroup by 5-6%.
 constexpr int64_t kTileRunMax = 16 * kTileOut;
@@ -98,7 +101,9 @@ struct JobArgs {
 };
 
 // kStratArg: the tile kernel carrying locations (arg max/min filter).
-enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3, kStratArg = 4 };
+// kStratTile2 / kStratArg2: the same kernels for 2048 < w <= 4096 (single
+// series, rows).
+enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3, kStratArg = 4, kStratTile2 = 5, kStratArg2 = 6 };
 
 // Occupancy-derived persistent grid sizes (computed once per device).
 int grid_cap(int dtype, int strategy);

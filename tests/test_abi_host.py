@@ -101,7 +101,9 @@ def test_planner(lib):
     assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_TILE
     assert binding.maxmin_plan(np.float32, 1 << 20, 1024) == binding.STRATEGY_TILE
     assert binding.maxmin_plan(np.float32, 1 << 20, 2048) == binding.STRATEGY_TILE
-    assert binding.maxmin_plan(np.float32, 1 << 20, 2049) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)
+    assert binding.maxmin_plan(np.float32, 1 << 20, 2049) == binding.STRATEGY_TILE
+    assert binding.maxmin_plan(np.float32, 1 << 20, 4096) == binding.STRATEGY_TILE
+    assert binding.maxmin_plan(np.float32, 1 << 20, 4097) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)
     binding.maxmin_set_strategy(binding.STRATEGY_CHUNK)
     assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_CHUNK
     binding.maxmin_set_strategy(binding.STRATEGY_TILE)

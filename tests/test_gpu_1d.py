@@ -67,8 +67,8 @@ def test_plain_all_windows(dt):
 def test_forced_strategies_agree(strategy):
     rng = synth.rng_for("tests", 101)
     for dt in DTS:
-        for w in [1, 2, 5, 33, 100, 512, 700, 1024, 1025, 1500, 2048] + \
-                 ([2049, 3000, 4097, 9000] if strategy != mm.STRATEGY_TILE else []):
+        for w in [1, 2, 5, 33, 100, 512, 700, 1024, 1025, 1500, 2048, 2049, 3000, 4096] + \
+                 ([4097, 9000] if strategy != mm.STRATEGY_TILE else []):
             n = int(rng.integers(w, 3 * 2048 + w))
             a = gen(n, dt, rng, "walk" if w % 2 else "ties")
             note("forced=%d dt=%s n=%d w=%d" % (strategy, np.dtype(dt).name, n, w))
@@ -141,7 +141,51 @@ def test_chunk_ticket_ranges(ranges, monkeypatch):
                      (5000, 2500 * 1400 + 77), (9000, 3000 * 1500 + 1234), (65536, 4096 * 1100 + 999)):
             a = gen(n, dt, rng, "walk")
             note("ranges=%s dt=%s n=%d w=%d" % (ranges, np.dtype(dt).name, n, w))
-            check(a, w, "ranges=%s n=%d w=%d" % (ranges, n, w))
+            check(a, w, "ranges=%s n=%d w=%d" % (ranges, n, w), strategy=mm.STRATEGY_CHUNK)
+
+
+@pytest.mark.parametrize("run", [None, "2048", "4096", "10000"])
+def test_tile_windows_over_two_subtiles(run, monkeypatch):
+    """2048 < w <= 4096: the tile kernel with blocks of a whole sub-tile,
+    whose windows end up to two sub-tiles after they start.  Runs of one,
+    two and four sub-tiles (so every run boundary re-reads a two-sub-tile
+    halo), n from a single window to several runs with a ragged tail,
+    ties and ramps, misaligned input and outputs, max-only and min-only."""
+    import torch
+    if run is not None:
+        monkeypatch.setenv("MAXMIN_TILE_RUN", run)
+    rng = synth.rng_for("tests", 108)
+    for dt in DTS:
+        tdt = to_dev(np.zeros(1, dt)).dtype
+        for w in (2049, 2050, 2304, 3000, 4095, 4096):
+            assert mm.maxmin_plan(dt, 1 << 20, w) == mm.STRATEGY_TILE
+            for n in sorted({w, w + 1, w + 2047, w + 2048, w + 4095, 3 * 2048 + w + 5, 9 * 2048 + 13}):
+                kind = ["walk", "ties", "ramp"][(n + w) % 3]
+                a = gen(n, dt, rng, kind)
+                note("tile2 run=%s dt=%s n=%d w=%d kind=%s" % (run, np.dtype(dt).name, n, w, kind))
+                check(a, w, "tile2 n=%d w=%d %s" % (n, w, kind))
+        # misaligned input and outputs; one output only
+        w, n = 3001, 40000 + 3
+        a = gen(n, dt, rng, "walk")
+        omx, omn = oracle.wedge(a, w)
+        no = n - w + 1
+        for oi, ox, on in ((1, 3, 2), (2, 0, 0)):
+            buf = to_dev(np.concatenate([np.zeros(oi, dt), a]))
+            bmx = torch.empty(no + 8, dtype=tdt, device="cuda")
+            bmn = torch.empty(no + 8, dtype=tdt, device="cuda")
+            note("tile2 misaligned run=%s dt=%s in=%d max=%d min=%d" % (run, np.dtype(dt).name, oi, ox, on))
+            mm.maxmin_filter(buf[oi:], w, bmx[ox:ox + no], bmn[on:on + no])
+            torch.cuda.synchronize()
+            assert_bits_equal(to_host(bmx[ox:ox + no], dt), omx, "tile2 max offsets %d/%d/%d" % (oi, ox, on))
+            assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "tile2 min offsets %d/%d/%d" % (oi, ox, on))
+        x = to_dev(a)
+        note("tile2 one output run=%s dt=%s" % (run, np.dtype(dt).name))
+        gmx, none = mm.maxmin_filter(x, w, which="max")
+        none2, gmn = mm.maxmin_filter(x, w, which="min")
+        assert none is None and none2 is None
+        torch.cuda.synchronize()
+        assert_bits_equal(to_host(gmx, dt), omx, "tile2 max-only")
+        assert_bits_equal(to_host(gmn, dt), omn, "tile2 min-only")
 
 
 def test_repeatable_bits():
@@ -158,7 +202,7 @@ def test_repeatable_bits():
             assert torch.equal(r[0], r0[0]) and torch.equal(r[1], r0[1])
 
 
-@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 5000])
+@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000])
 def test_stream_chunks_equal_one_shot(w):
     import torch
     rng = synth.rng_for("tests", 106)

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 DTS = [np.float32, np.float64, np.int32, np.uint16]
 WINDOWS = [1, 2, 3, 7, 8, 9, 16, 63, 64, 65, 255, 256, 511, 512, 513, 1000, 1024, 1025, 1500, 2048, 2049,
-           4097, 10000, 70000]
+           3000, 4095, 4096, 4097, 8193, 10000, 65536, 70000]
 
 
 def _data(n, dt, rng, ties):
@@ -90,7 +90,7 @@ def test_argfilter_misaligned():
 
 @pytest.mark.timeout(600)
 def test_argfilter_full_size_sampled():
-    """n = 2^28 float32 walk at windows 256 and 4096 (a doubling step):
+    """n = 2^28 float32 walk at windows 256, 4096 and 65536 (a combine step):
     sampled windows against the definition (numpy's first-occurrence argmax
     over the window), every location inside its window, and the values at
     the locations equal to the max/min outputs."""
@@ -99,7 +99,7 @@ def test_argfilter_full_size_sampled():
     a = synth.large_series("walk", n)
     x = to_dev(a)
     rng = np.random.default_rng(7)
-    for w in (256, 4096):
+    for w in (256, 4096, 65536):
         note("arg full size w=%d" % w)
         mx, mn, ix, in_ = mm.maxmin_argfilter(x, w)
         torch.cuda.synchronize()
