@@ -2,8 +2,9 @@
 
 A step is one pass of the hot path over the n = 2**28 float32 random-walk
 series: the running max and min at each of the windows 16, 256, 4096 and
-65536 (four launches; the tile strategy serves the first two, the chunk
-strategy the last two).  ``value`` is input elements processed per second over
+65536 (four launches; the tile kernel serves the first three -- its
+instantiation for windows over one sub-tile at w = 4096 -- and the chunk
+kernel the last).  ``value`` is input elements processed per second over
 the K timed steps (Gelem/s), inputs already resident in HBM.
 
 Also reported on the same JSON line (not part of ``value``):
@@ -44,9 +45,12 @@ def alg_bytes(n, w, s):
     return n * s + 2 * max(0, n - w + 1) * s
 
 
-def kernel_name(strategy):
-    # as rocprofv3 names the single-series float32 instantiations
-    return "mm::k_tile<0, float, false>" if strategy == "tile" else "mm::k_%s<0, float>" % strategy
+def kernel_name(strategy, w):
+    # as rocprofv3 names the single-series float32 instantiations (the tile
+    # kernel's last template argument: windows end one or two sub-tiles on)
+    if strategy == "tile":
+        return "mm::k_tile<0, float, false, %d>" % (1 if w <= 2048 else 2)
+    return "mm::k_%s<0, float>" % strategy
 
 
 # Sources whose change invalidates counter-derived traffic figures.
@@ -176,7 +180,7 @@ def main():
     # point is its algorithmic bytes over its launches / their total time
     kern = {}
     for w in WINDOWS:
-        k = kernel_name(per_window[str(w)]["strategy"])
+        k = kernel_name(per_window[str(w)]["strategy"], w)
         kern.setdefault(k, []).append(w)
     dom = max(kern, key=lambda k: sum(np.mean(ev[w]) for w in kern[k]))
     dom_ms = float(np.mean([t for w in kern[dom] for t in ev[w]]))
