@@ -57,6 +57,7 @@ def lib():
         L.maxmin_envelope_batched.argtypes = [ci, vp, vp, vp, i64, vp, vp, vp]
         L.maxmin_set_strategy.argtypes = [ci]
         L.maxmin_plan.argtypes = [ci, i64, i64]
+        L.maxmin_plan_2d.argtypes = [ci, i64, i64]
         L.maxmin_check_stream.argtypes = [vp]
         vpp = ctypes.POINTER(vp)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -81,7 +82,7 @@ def lib():
                   "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_morph_2d",
                   "maxmin_envelope", "maxmin_envelope_batched", "maxmin_autotune", "maxmin_tuning",
                   "maxmin_set_strategy",
-                  "maxmin_plan", "maxmin_check_stream"):
+                  "maxmin_plan", "maxmin_plan_2d", "maxmin_check_stream"):
             getattr(L, f).restype = ci
         _lib = L
         return L
@@ -345,6 +346,17 @@ def maxmin_set_strategy(strategy):
 
 def maxmin_plan(dtype, n, w):
     return lib().maxmin_plan(dtype_code(dtype), int(n), int(w))
+
+
+PLAN_2D_FUSED, PLAN_2D_ROWS_COLS = 1, 2
+
+
+def maxmin_plan_2d(dtype, w_rows, w_cols):
+    """PLAN_2D_FUSED (one pass) or PLAN_2D_ROWS_COLS for these windows."""
+    r = lib().maxmin_plan_2d(dtype_code(dtype), int(w_rows), int(w_cols))
+    if r not in (PLAN_2D_FUSED, PLAN_2D_ROWS_COLS):
+        _check(r)
+    return r
 
 
 def maxmin_check_stream(stream=None):

@@ -113,6 +113,21 @@ int plan_strategy(int dt, int64_t n, int64_t w) {
   return MAXMIN_STRATEGY_CHUNK;
 }
 
+// The fused 2-D pass serves the windows it fits, except column windows of
+// 16 rows or more for 4- and 8-byte data: there its one column per lane
+// and the 32- or 64-row ring lost to rows-then-columns on MI355X (8192^2
+// float32: w = 24 / 31 / 63 in 0.54 / 0.54 / 1.11 ms against 0.50 / 0.50 /
+// 0.65 ms), while 16-bit data gain throughout (uint16 w = 31 / 63: 0.38 /
+// 0.77 against 0.63 / 0.94 ms).  MAXMIN_2D_FUSED=0 / =1 force either path
+// where both apply (experiments and tests).
+bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols) {
+  if (!mm::f2d_eligible(dtype, w_rows, w_cols)) return false;
+  const char* e = getenv("MAXMIN_2D_FUSED");
+  if (e && !strcmp(e, "0")) return false;
+  if (e && !strcmp(e, "1")) return true;
+  return w_rows < 16 || dsize(dtype) == 2;
+}
+
 // Which tile kernel a single series or a row pass of window w runs.
 int tile_kind(int64_t w) { return w <= mm::kTileMaxW ? mm::kStratTile : mm::kStratTile2; }
 
@@ -360,6 +375,12 @@ int maxmin_set_strategy(int strategy) {
 }
 
 int maxmin_plan(int dtype, int64_t n, int64_t w) { return plan_strategy(dtype, n, w); }
+
+int maxmin_plan_2d(int dtype, int64_t w_rows, int64_t w_cols) {
+  if (!dsize(dtype)) return fail(MAXMIN_EINVAL, "maxmin_plan_2d: unknown dtype %d", dtype);
+  if (w_rows < 1 || w_cols < 1) return fail(MAXMIN_EINVAL, "maxmin_plan_2d: window < 1");
+  return fused_2d(dtype, w_rows, w_cols) ? MAXMIN_2D_FUSED : MAXMIN_2D_ROWS_COLS;
+}
 
 int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max, void* d_min, void* stream) {
   const size_t s = dsize(dtype);
@@ -625,9 +646,17 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   if (!d_in || (!d_max && !d_min)) return fail(MAXMIN_EINVAL, "maxmin_filter_2d: null pointer");
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s))
     return fail(MAXMIN_EINVAL, "maxmin_filter_2d: pointer not aligned to the element size");
+  hipStream_t st = (hipStream_t)stream;
+  // one fused pass when the windows fit it (no intermediate images)
+  if (fused_2d(dtype, w_rows, w_cols)) {
+    const char* eb = getenv("MAXMIN_2D_BAND");
+    hipError_t e = mm::launch_f2d(dtype, d_in, ld_in, rows, cols, w_rows, w_cols, d_max, d_min, ld_out,
+                                  eb ? atoll(eb) : 0, st);
+    if (e == hipSuccess) return ok();
+    if (e != hipErrorNotSupported) return hip_fail(e, "maxmin_filter_2d (fused)");
+  }
   if ((orows + w_rows - 1) / w_rows > 65535)
     return fail(MAXMIN_EUNSUPPORTED, "maxmin_filter_2d: too many row blocks for one launch");
-  hipStream_t st = (hipStream_t)stream;
   Workspace* ws = nullptr;
   int r = get_ws(st, &ws);
   if (r) return r;

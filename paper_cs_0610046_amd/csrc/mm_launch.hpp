@@ -145,6 +145,14 @@ int set_error(int code, const char* msg);
 hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
                        int64_t wr, void* d_max, void* d_min, int64_t ld_out, void* gscratch, hipStream_t st);
 int64_t cols_max_window(int dtype);
+
+// Fused 2-D filter (one pass, no intermediate images) for w_rows <= 64 and
+// w_cols <= 64 * V + 1 (V = 4, 4, 4, 2, 1, 1 for column blocks 1..32);
+// hipErrorNotSupported when the windows do not fit.  band_rows <= 0: the
+// launcher picks the band height.
+bool f2d_eligible(int dtype, int64_t w_rows, int64_t w_cols);
+hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, int64_t cols, int64_t w_rows,
+                      int64_t w_cols, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows, hipStream_t st);
 int64_t cols_scratch_elems(int64_t rows, int64_t oc, int64_t wr);
 
 }  // namespace mm

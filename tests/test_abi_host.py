@@ -96,6 +96,27 @@ def test_out_offsets_matches_oracle(lib):
         binding.maxmin_out_offsets(np.array([0, 5], np.int64), np.array([0], np.int64))
 
 
+def test_planner_2d(lib, monkeypatch):
+    """The 2-D path choice: the fused pass for the windows it fits (w_rows
+    <= 64, w_cols <= 64 V + 1), except w_rows >= 16 for 4- and 8-byte data."""
+    monkeypatch.delenv("MAXMIN_2D_FUSED", raising=False)
+    F, RC = binding.PLAN_2D_FUSED, binding.PLAN_2D_ROWS_COLS
+    for dt in (np.float32, np.float64, np.int32, np.uint16):
+        assert binding.maxmin_plan_2d(dt, 3, 3) == F
+        assert binding.maxmin_plan_2d(dt, 7, 257) == F and binding.maxmin_plan_2d(dt, 7, 258) == RC
+        assert binding.maxmin_plan_2d(dt, 15, 129) == F and binding.maxmin_plan_2d(dt, 15, 130) == RC
+        big = F if dt == np.uint16 else RC
+        assert binding.maxmin_plan_2d(dt, 16, 65) == big and binding.maxmin_plan_2d(dt, 31, 66) == RC
+        assert binding.maxmin_plan_2d(dt, 63, 63) == big
+        assert binding.maxmin_plan_2d(dt, 65, 1) == RC
+    monkeypatch.setenv("MAXMIN_2D_FUSED", "1")
+    assert binding.maxmin_plan_2d(np.float32, 63, 63) == F
+    monkeypatch.setenv("MAXMIN_2D_FUSED", "0")
+    assert binding.maxmin_plan_2d(np.float32, 3, 3) == RC
+    with pytest.raises(binding.MaxMinError):
+        binding.maxmin_plan_2d(np.float32, 0, 3)
+
+
 def test_planner(lib):
     binding.maxmin_set_strategy(binding.STRATEGY_AUTO)
     assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_TILE
