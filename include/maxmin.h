@@ -291,7 +291,7 @@ int maxmin_set_strategy(int strategy);
 int maxmin_plan(int dtype, int64_t n, int64_t w);
 
 /* Path maxmin_filter_2d takes for (dtype, w_rows, w_cols): MAXMIN_2D_FUSED
- * (one pass, no intermediate images: w_rows < 16, or w_rows <= 64 for
+ * (one pass, no intermediate images: w_rows < 16, or w_rows < 32 for
  * 16-bit data, and w_cols <= 64 V + 1 with V = 4 for w_rows < 8, 2 for
  * w_rows < 16, else 1) or MAXMIN_2D_ROWS_COLS (rows, then columns through
  * two library-owned intermediate images).  EINVAL for an unknown dtype or a

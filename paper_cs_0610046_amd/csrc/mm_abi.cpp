@@ -113,20 +113,26 @@ int plan_strategy(int dt, int64_t n, int64_t w) {
   return MAXMIN_STRATEGY_CHUNK;
 }
 
-// The fused 2-D pass serves the windows it fits, except column windows of
-// 16 rows or more for 4- and 8-byte data: there its one column per lane
-// and the 32- or 64-row ring lost to rows-then-columns on MI355X (8192^2
-// float32: w = 24 / 31 / 63 in 0.54 / 0.54 / 1.11 ms against 0.50 / 0.50 /
-// 0.65 ms), while 16-bit data gain throughout (uint16 w = 31 / 63: 0.38 /
-// 0.77 against 0.63 / 0.94 ms).  MAXMIN_2D_FUSED=0 / =1 force either path
-// where both apply (experiments and tests).
+// The fused 2-D pass serves the windows it fits up to 15 rows (4- and
+// 8-byte data) or 31 rows (16-bit data); past those its one column per
+// lane and the 32- or 64-row LDS ring lose to rows-then-columns.  On MI355X
+// (8192^2): float32 w = 24 / 31 / 63 fused 0.54 / 0.54 / 1.11 ms against
+// 0.50 / 0.50 / 0.65 ms; uint16 w = 31 / 63 fused 0.38 / 0.77 ms against
+// 0.40 / 0.60 ms.  MAXMIN_2D_FUSED=0 / =1 force either path where both
+// apply (experiments and tests).
 bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols) {
   if (!mm::f2d_eligible(dtype, w_rows, w_cols)) return false;
   const char* e = getenv("MAXMIN_2D_FUSED");
   if (e && !strcmp(e, "0")) return false;
   if (e && !strcmp(e, "1")) return true;
-  return w_rows < 16 || dsize(dtype) == 2;
+  return w_rows < (dsize(dtype) == 2 ? 32 : 16);
 }
+// Column pass of rows-then-columns: the fused kernel's column filter alone
+// (streaming down bands) for windows under 16 rows and for 16-bit data,
+// else blocks of w_rows rows (on MI355X, 8192^2 float32, w = 31 / 63: 0.31
+// / 0.47 ms against 0.50 / 0.87 ms for the streaming filter; uint16 w =
+// 63: 0.80 against 0.45 ms the other way).
+bool stream_cols_2d(int dtype, int64_t w_rows) { return w_rows < 16 || (dsize(dtype) == 2 && w_rows <= 64); }
 
 // Which tile kernel a single series or a row pass of window w runs.
 int tile_kind(int64_t w) { return w <= mm::kTileMaxW ? mm::kStratTile : mm::kStratTile2; }
@@ -700,7 +706,12 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
     e = mm::launch_1d(dtype, mm::kStratChunk, a, (int)std::min<int64_t>(a.ntiles, mm::grid_cap(dtype, mm::kStratChunk)), st);
   }
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (rows)");
-  e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
+  // column pass
+  e = stream_cols_2d(dtype, w_rows)
+          ? mm::launch_f2d_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, 0, st)
+          : hipErrorNotSupported;
+  if (e == hipErrorNotSupported)
+    e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (columns)");
   return ok();
 }

@@ -124,6 +124,7 @@ typedef unsigned int f2_u32x2 __attribute__((ext_vector_type(2)));
 
 template <class T> struct F2dArgs {
   const T* in;
+  const T* in2;  // column-only mode: the row-filtered min image (in: the max image)
   int64_t ld_in, rows, cols;
   int wr, wc;
   T* omax;
@@ -204,6 +205,26 @@ template <class T, int V> __device__ __forceinline__ void f2_store(T* p, const T
 // No lane-dependent branch: a branch whose sides write the load's
 // registers would make every lane wait for the load; strips that reach the
 // row end (a wave-uniform test) clamp each column instead.
+// Column-only mode: the V columns of row `row` of the two row-filtered
+// images (max into x, min into h), clamped at the row end like the above.
+template <class T, int V, bool VIN>
+__device__ __forceinline__ void f2_pair_load(const F2dArgs<T>& a, int64_t row, int64_t c0, T (&x)[V], T (&h)[V]) {
+  const int lane = threadIdx.x & 63;
+  const T* px = a.in + row * a.ld_in;
+  const T* pn = a.in2 + row * a.ld_in;
+  const int64_t cm = c0 + lane * V;
+  if (c0 + 64 * V <= a.cols) {
+    f2_load<T, V, VIN>(px + cm, x);
+    f2_load<T, V, VIN>(pn + cm, h);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      x[i] = gload(px + min(cm + i, a.cols - 1));
+      h[i] = gload(pn + min(cm + i, a.cols - 1));
+    }
+  }
+}
+
 template <class T, int V, bool VIN>
 __device__ __forceinline__ void f2_row_load(const F2dArgs<T>& a, int64_t row, int64_t c0, T (&x)[V], T (&h)[V]) {
   constexpr int W = 64 * V;
@@ -261,7 +282,10 @@ __device__ __forceinline__ void f2_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class T, int B, int V, bool VIN>
+// COLS: column-only mode, the input being the pair of row-filtered images
+// (the second pass of rows-then-columns): the same column filter, no row
+// work, no halo columns.
+template <class T, int B, int V, bool VIN, bool COLS>
 __global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
   constexpr int W = 64 * V;                     // output columns per strip
   constexpr int RB = 2 * B;                     // ring rows
@@ -296,7 +320,10 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
   T bx[D][V], bh[D][V];
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    if (d < NR) f2_row_load<T, V, VIN>(a, r0 + d, c0, bx[d], bh[d]);
+    if (d < NR) {
+      if constexpr (COLS) f2_pair_load<T, V, VIN>(a, r0 + d, c0, bx[d], bh[d]);
+      else f2_row_load<T, V, VIN>(a, r0 + d, c0, bx[d], bh[d]);
+    }
   T Px[V], Pn[V], Ax[V], An[V];  // running column PRE; aggregate of the last whole block
 #pragma unroll
   for (int i = 0; i < V; ++i) {
@@ -308,6 +335,15 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
     for (int d = 0; d < D; ++d) {
       const int t = t0 + d;
       if (t < NR) {
+        T rx[V], rn[V];  // the row-filtered values of this lane's columns
+        if constexpr (COLS) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            rx[i] = bx[d][i];
+            rn[i] = bh[d][i];
+          }
+          if (t + D < NR) f2_pair_load<T, V, VIN>(a, r0 + t + D, c0, bx[d], bh[d]);
+        } else {
         // ---- along the row
         T px[V], pn[V], qx[V], qn[V], sx[V], sn[V];
         px[0] = pn[0] = bx[d][0];
@@ -364,7 +400,6 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
           hpn[lds_idx<T>(W + lane * V + i)] = qn[i];
         }
         f2_wave_sync();
-        T rx[V], rn[V];  // the row-filtered values of this lane's columns
 #pragma unroll
         for (int i = 0; i < V; ++i) {
           const int cc = lane * V + i, e = cc + wc - 1, b1 = cc >> lgBh;
@@ -381,6 +416,7 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
         f2_wave_sync();  // the row buffer is rewritten by the next row
         // the next loads into this slot of the row queue
         if (t + D < NR) f2_row_load<T, V, VIN>(a, r0 + t + D, c0, bx[d], bh[d]);
+        }
         // ---- down the columns
         const int slot = t & (RB - 1);
         if ((t & (B - 1)) == 0 && t > 0) {
@@ -460,18 +496,22 @@ bool f2d_eligible(int dtype, int64_t w_rows, int64_t w_cols) {
   return w_cols <= 64 * f2d_V(B, f2d_size(dtype)) + 1;
 }
 
-template <class T, int B, int V>
+template <class T, int B, int V, bool COLS>
 static hipError_t f2d_go(const F2dArgs<T>& a, int64_t grid, hipStream_t st) {
   const size_t al = std::min<size_t>(16, (size_t)V * sizeof(T));
-  const bool vin = al >= 4 && (uintptr_t)a.in % al == 0 && ((size_t)a.ld_in * sizeof(T)) % al == 0;
-  if (vin) hipLaunchKernelGGL((k_f2d<T, B, V, true>), dim3((unsigned)grid), dim3(64), 0, st, a);
-  else hipLaunchKernelGGL((k_f2d<T, B, V, false>), dim3((unsigned)grid), dim3(64), 0, st, a);
+  const bool vin = al >= 4 && (uintptr_t)a.in % al == 0 && (uintptr_t)a.in2 % al == 0 &&
+                   ((size_t)a.ld_in * sizeof(T)) % al == 0;
+  if (vin) hipLaunchKernelGGL((k_f2d<T, B, V, true, COLS>), dim3((unsigned)grid), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL((k_f2d<T, B, V, false, COLS>), dim3((unsigned)grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, int64_t cols, int64_t w_rows,
-                      int64_t w_cols, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows, hipStream_t st) {
-  if (!f2d_eligible(dtype, w_rows, w_cols)) return hipErrorNotSupported;
+// Shared launcher: COLS = column-only mode (in, in2: the row-filtered max
+// and min images, w_cols = 1).
+template <bool COLS>
+static hipError_t f2d_launch(int dtype, const void* d_in, const void* d_in2, int64_t ld_in, int64_t rows,
+                             int64_t cols, int64_t w_rows, int64_t w_cols, void* d_max, void* d_min, int64_t ld_out,
+                             int64_t band_rows, hipStream_t st) {
   const int64_t orows = rows - w_rows + 1, oc = cols - w_cols + 1;
   if (orows <= 0 || oc <= 0) return hipSuccess;
   int B = 1;
@@ -496,6 +536,7 @@ hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, 
     using T = std::remove_pointer_t<decltype(p)>;
     F2dArgs<T> a;
     a.in = (const T*)d_in;
+    a.in2 = (const T*)d_in2;
     a.ld_in = ld_in;
     a.rows = rows;
     a.cols = cols;
@@ -508,12 +549,12 @@ hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, 
     a.TR = (int)TR;
     a.ntiles = ntiles;
     switch (B) {
-      case 1: return f2d_go<T, 1, 4>(a, grid, st);
-      case 2: return f2d_go<T, 2, 4>(a, grid, st);
-      case 4: return f2d_go<T, 4, 4>(a, grid, st);
-      case 8: return f2d_go<T, 8, 2>(a, grid, st);
-      case 16: return f2d_go<T, 16, 1>(a, grid, st);
-      default: return f2d_go<T, 32, 1>(a, grid, st);
+      case 1: return f2d_go<T, 1, 4, COLS>(a, grid, st);
+      case 2: return f2d_go<T, 2, 4, COLS>(a, grid, st);
+      case 4: return f2d_go<T, 4, 4, COLS>(a, grid, st);
+      case 8: return f2d_go<T, 8, 2, COLS>(a, grid, st);
+      case 16: return f2d_go<T, 16, 1, COLS>(a, grid, st);
+      default: return f2d_go<T, 32, 1, COLS>(a, grid, st);
     }
   };
   switch (dtype) {
@@ -523,6 +564,24 @@ hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, 
     case 3: return go((uint16_t*)nullptr);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, int64_t cols, int64_t w_rows,
+                      int64_t w_cols, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows, hipStream_t st) {
+  if (!f2d_eligible(dtype, w_rows, w_cols)) return hipErrorNotSupported;
+  return f2d_launch<false>(dtype, d_in, d_in, ld_in, rows, cols, w_rows, w_cols, d_max, d_min, ld_out, band_rows,
+                           st);
+}
+
+hipError_t launch_f2d_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
+                           int64_t w_rows, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows,
+                           hipStream_t st) {
+  if (dtype < 0 || dtype > 3 || w_rows < 1 || w_rows > 64) return hipErrorNotSupported;
+  if (!tmax && !tmin) return hipErrorInvalidValue;
+  // a missing image (one output only) reads the other one in its place
+  const void* a = tmax ? tmax : tmin;
+  const void* b = tmin ? tmin : tmax;
+  return f2d_launch<true>(dtype, a, b, ld_t, rows, oc, w_rows, 1, d_max, d_min, ld_out, band_rows, st);
 }
 
 int64_t cols_max_window(int dtype) {

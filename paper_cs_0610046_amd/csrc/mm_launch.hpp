@@ -153,6 +153,13 @@ int64_t cols_max_window(int dtype);
 bool f2d_eligible(int dtype, int64_t w_rows, int64_t w_cols);
 hipError_t launch_f2d(int dtype, const void* d_in, int64_t ld_in, int64_t rows, int64_t cols, int64_t w_rows,
                       int64_t w_cols, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows, hipStream_t st);
+// The same kernel's column filter alone, as the second pass of
+// rows-then-columns over the row-filtered images (rows x oc, leading
+// dimension ld_t; either may be null for a one-output call): w_rows <= 64,
+// else hipErrorNotSupported (launch_cols serves those).
+hipError_t launch_f2d_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
+                           int64_t w_rows, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows,
+                           hipStream_t st);
 int64_t cols_scratch_elems(int64_t rows, int64_t oc, int64_t wr);
 
 }  // namespace mm
