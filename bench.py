@@ -16,7 +16,8 @@ Also reported on the same JSON line (not part of ``value``):
 * ``plain``        -- n = 2**20 float32, w = 64 (latency-bound),
 * ``batched``      -- 10,000 float32 random walks, lengths log-uniform in
   [1e3, 1e6], windows uniform in [2, 1024], one batched call (graph replay),
-* ``image``        -- 8192 x 8192 float32, w x w windows, rows then columns,
+* ``image``        -- 8192 x 8192 float32 (``image_u16``: uint16), w x w windows,
+  one fused pass or rows then columns (the ``path`` field),
 * ``argfilter``    -- n = 2**28 float32 walk, values plus leftmost locations,
 * ``max_only``     -- the same walk, w = 256, only the max output,
 * ``envelope``     -- centered envelopes of 100,000 walks of 1024 samples,
@@ -268,25 +269,33 @@ def run_extras(torch, mm, synth, dev, stream):
     print("[bench] batched %.3f ms" % ms, file=sys.stderr, flush=True)
     del xb, bmx, bmn
 
-    # image: 8192 x 8192 float32 Gaussian field, w x w
-    img = synth.gaussian_field(8192, 8192)
-    xi = torch.from_numpy(img).to(dev)
-    del img
-    res = {}
-    for w in (3, 15, 63):
-        o1 = torch.empty((8192 - w + 1, 8192 - w + 1), device=dev)
-        o2 = torch.empty_like(o1)
-        for _ in range(2):
-            mm.maxmin_filter_2d(xi, w, w, o1, o2)
-        ts = timed(lambda: mm.maxmin_filter_2d(xi, w, w, o1, o2), 5, stream)
-        ms = float(np.median(ts))
-        ab = 8192 * 8192 * 4 + 2 * o1.numel() * 4
-        res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(8192 * 8192 / (ms * 1e-3) / 1e9, 2),
-                       "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
-        del o1, o2
-    out["image"] = {"workload": "8192x8192 float32 Gaussian field + noise, rows then columns", "per_window": res}
-    print("[bench] image done", file=sys.stderr, flush=True)
-    del xi
+    # image: 8192 x 8192, float32 Gaussian field and uint16 uniform, w x w
+    for key, make, s in (("image", lambda: synth.gaussian_field(8192, 8192), 4),
+                         ("image_u16", lambda: synth.uniform_u16((8192, 8192), synth.rng_for("image", 1)), 2)):
+        img = make()
+        if img.dtype == np.uint16:  # bit-for-bit through int16 (torch's uint16 has few ops)
+            xi = torch.from_numpy(img.view(np.int16)).view(torch.uint16).to(dev)
+        else:
+            xi = torch.from_numpy(img).to(dev)
+        del img
+        res = {}
+        for w in (3, 15, 63):
+            o1 = torch.empty((8192 - w + 1, 8192 - w + 1), device=dev, dtype=xi.dtype)
+            o2 = torch.empty_like(o1)
+            for _ in range(2):
+                mm.maxmin_filter_2d(xi, w, w, o1, o2)
+            ts = timed(lambda: mm.maxmin_filter_2d(xi, w, w, o1, o2), 5, stream)
+            ms = float(np.median(ts))
+            ab = 8192 * 8192 * s + 2 * o1.numel() * s
+            plan = mm.maxmin_plan_2d(xi.dtype, w, w)
+            res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(8192 * 8192 / (ms * 1e-3) / 1e9, 2),
+                           "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
+                           "path": "fused" if plan == mm.PLAN_2D_FUSED else "rows then columns"}
+            del o1, o2
+        out[key] = {"workload": "8192x8192 %s, w x w windows (algorithmic bytes: input + both outputs)" %
+                    ("float32 Gaussian field + noise" if s == 4 else "uint16 uniform"), "per_window": res}
+        print("[bench] %s done" % key, file=sys.stderr, flush=True)
+        del xi
 
     # arg filter: n = 2^28 float32 walk, values and leftmost locations
     xa = torch.from_numpy(synth.random_walk(1 << 28, np.float32, synth.rng_for("large", 0))).to(dev)
