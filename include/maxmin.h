@@ -290,14 +290,15 @@ int maxmin_set_strategy(int strategy);
 /* Strategy the planner would use for (dtype, n, w): a maxmin_strategy_t. */
 int maxmin_plan(int dtype, int64_t n, int64_t w);
 
-/* Path maxmin_filter_2d takes for (dtype, w_rows, w_cols): MAXMIN_2D_FUSED
- * (one pass, no intermediate images: w_rows < 16, or w_rows < 32 for
- * 16-bit data, and w_cols <= 64 V + 1 with V = 4 for w_rows < 8, 2 for
+/* Path maxmin_filter_2d takes for (dtype, w_rows, w_cols) with `outputs`
+ * (2: max and min; 1: one of them null): MAXMIN_2D_FUSED (one pass, no
+ * intermediate images: w_rows < 16, or w_rows < 32 for 16-bit data or one
+ * output, and w_cols <= 64 V + 1 with V = 4 for w_rows < 8, 2 for
  * w_rows < 16, else 1) or MAXMIN_2D_ROWS_COLS (rows, then columns through
- * two library-owned intermediate images).  EINVAL for an unknown dtype or a
- * window < 1.  Host only. */
+ * two library-owned intermediate images).  EINVAL for an unknown dtype, a
+ * window < 1 or outputs not 1 or 2.  Host only. */
 enum { MAXMIN_2D_FUSED = 1, MAXMIN_2D_ROWS_COLS = 2 };
-int maxmin_plan_2d(int dtype, int64_t w_rows, int64_t w_cols);
+int maxmin_plan_2d(int dtype, int64_t w_rows, int64_t w_cols, int outputs);
 
 /* Synchronise `stream` (void* hipStream_t) and check the library's device
  * status words for it: MAXMIN_EDEVICE if a chunk-strategy look-back wait on

@@ -57,7 +57,7 @@ def lib():
         L.maxmin_envelope_batched.argtypes = [ci, vp, vp, vp, i64, vp, vp, vp]
         L.maxmin_set_strategy.argtypes = [ci]
         L.maxmin_plan.argtypes = [ci, i64, i64]
-        L.maxmin_plan_2d.argtypes = [ci, i64, i64]
+        L.maxmin_plan_2d.argtypes = [ci, i64, i64, ci]
         L.maxmin_check_stream.argtypes = [vp]
         vpp = ctypes.POINTER(vp)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -351,9 +351,10 @@ def maxmin_plan(dtype, n, w):
 PLAN_2D_FUSED, PLAN_2D_ROWS_COLS = 1, 2
 
 
-def maxmin_plan_2d(dtype, w_rows, w_cols):
-    """PLAN_2D_FUSED (one pass) or PLAN_2D_ROWS_COLS for these windows."""
-    r = lib().maxmin_plan_2d(dtype_code(dtype), int(w_rows), int(w_cols))
+def maxmin_plan_2d(dtype, w_rows, w_cols, outputs=2):
+    """PLAN_2D_FUSED (one pass) or PLAN_2D_ROWS_COLS for these windows, for
+    a call with both outputs (outputs=2) or one (outputs=1)."""
+    r = lib().maxmin_plan_2d(dtype_code(dtype), int(w_rows), int(w_cols), int(outputs))
     if r not in (PLAN_2D_FUSED, PLAN_2D_ROWS_COLS):
         _check(r)
     return r

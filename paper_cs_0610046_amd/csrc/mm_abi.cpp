@@ -114,18 +114,20 @@ int plan_strategy(int dt, int64_t n, int64_t w) {
 }
 
 // The fused 2-D pass serves the windows it fits up to 15 rows (4- and
-// 8-byte data) or 31 rows (16-bit data); past those its one column per
-// lane and the 32- or 64-row LDS ring lose to rows-then-columns.  On MI355X
+// 8-byte data, both outputs) or 31 rows (16-bit data, or one output: its
+// LDS ring is then half the size); past those its one column per lane and
+// the 32- or 64-row LDS ring lose to rows-then-columns.  On MI355X
 // (8192^2): float32 w = 24 / 31 / 63 fused 0.54 / 0.54 / 1.11 ms against
 // 0.50 / 0.50 / 0.65 ms; uint16 w = 31 / 63 fused 0.38 / 0.77 ms against
-// 0.40 / 0.60 ms.  MAXMIN_2D_FUSED=0 / =1 force either path where both
-// apply (experiments and tests).
-bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols) {
+// 0.40 / 0.60 ms; float32 max-only w = 31 / 63 fused 0.31 / 0.56 ms
+// against 0.36 / 0.52 ms.  MAXMIN_2D_FUSED=0 / =1 force either path where
+// both apply (experiments and tests).
+bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols, bool one_output) {
   if (!mm::f2d_eligible(dtype, w_rows, w_cols)) return false;
   const char* e = getenv("MAXMIN_2D_FUSED");
   if (e && !strcmp(e, "0")) return false;
   if (e && !strcmp(e, "1")) return true;
-  return w_rows < (dsize(dtype) == 2 ? 32 : 16);
+  return w_rows < (dsize(dtype) == 2 || one_output ? 32 : 16);
 }
 // Column pass of rows-then-columns: the fused kernel's column filter alone
 // (streaming down bands) for windows under 16 rows and for 16-bit data,
@@ -382,10 +384,11 @@ int maxmin_set_strategy(int strategy) {
 
 int maxmin_plan(int dtype, int64_t n, int64_t w) { return plan_strategy(dtype, n, w); }
 
-int maxmin_plan_2d(int dtype, int64_t w_rows, int64_t w_cols) {
+int maxmin_plan_2d(int dtype, int64_t w_rows, int64_t w_cols, int outputs) {
   if (!dsize(dtype)) return fail(MAXMIN_EINVAL, "maxmin_plan_2d: unknown dtype %d", dtype);
   if (w_rows < 1 || w_cols < 1) return fail(MAXMIN_EINVAL, "maxmin_plan_2d: window < 1");
-  return fused_2d(dtype, w_rows, w_cols) ? MAXMIN_2D_FUSED : MAXMIN_2D_ROWS_COLS;
+  if (outputs != 1 && outputs != 2) return fail(MAXMIN_EINVAL, "maxmin_plan_2d: outputs=%d (1 or 2)", outputs);
+  return fused_2d(dtype, w_rows, w_cols, outputs == 1) ? MAXMIN_2D_FUSED : MAXMIN_2D_ROWS_COLS;
 }
 
 int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max, void* d_min, void* stream) {
@@ -654,7 +657,7 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
     return fail(MAXMIN_EINVAL, "maxmin_filter_2d: pointer not aligned to the element size");
   hipStream_t st = (hipStream_t)stream;
   // one fused pass when the windows fit it (no intermediate images)
-  if (fused_2d(dtype, w_rows, w_cols)) {
+  if (fused_2d(dtype, w_rows, w_cols, !d_max || !d_min)) {
     const char* eb = getenv("MAXMIN_2D_BAND");
     hipError_t e = mm::launch_f2d(dtype, d_in, ld_in, rows, cols, w_rows, w_cols, d_max, d_min, ld_out,
                                   eb ? atoll(eb) : 0, st);

@@ -1,0 +1,497 @@
+// gfx950 fused 2-D filter (Section 1: the 1-D filter on rows, then on
+// columns, here in one pass) -- kernel and launcher templates, instantiated
+// per output set in mm_kernels_2d*.hip.
+#pragma once
+
+#include <algorithm>
+#include <type_traits>
+
+#include "mm_launch.hpp"
+
+namespace mm {
+
+// One pass over the image for w_rows <= 64 and w_cols <= 64 * V + 1: a
+// wavefront owns a strip of 64*V output columns and a band of output rows
+// and streams down the band's input rows.  Each row is filtered along the
+// row in registers (blocks of Bh columns, PRE through an LDS row buffer,
+// SUF in registers: the 1-D tile scheme on one row of 64*V + w_cols - 1
+// inputs); the row results then feed a column filter with blocks of B
+// rows, kept per lane in an LDS ring of 2B rows: a block's raw values turn
+// into its suffixes when the next block starts, and the output of the
+// window that ends at the current row is
+//     max(SUF[first row], aggregate of the block between, running PRE).
+// Every lane owns its columns of the ring, so only the row buffer needs
+// barriers.  The max and min images never leave the chip: HBM traffic is
+// the input (plus the halo rows and columns) and the outputs.
+typedef unsigned int f2_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int f2_u32x2 __attribute__((ext_vector_type(2)));
+
+template <class T> struct F2dArgs {
+  const T* in;
+  const T* in2;  // column-only mode: the row-filtered min image (in: the max image)
+  int64_t ld_in, rows, cols;
+  int wr, wc;
+  T* omax;
+  T* omin;
+  int64_t ld_out;
+  int strips, TR;
+  int64_t ntiles;
+};
+
+// V consecutive elements at p.  Stores take the widest access (16, 8 or 4
+// bytes) that p's alignment allows; lane offsets are multiples of V * s, so
+// every lane of a wavefront takes the same branch for a given row.
+template <class T, int V, bool VIN> __device__ __forceinline__ void f2_load(const T* p, T (&x)[V]) {
+  // VIN: the launcher checked that every row start is aligned to the
+  // access width (min(16, V * s) bytes); a branch on the address here would
+  // make the compiler wait for each load where the branches join
+  constexpr int NB = V * (int)sizeof(T);
+  if constexpr (VIN && NB % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < NB / 16; ++k) {
+      const f2_u32x4 u = gload((const f2_u32x4*)p + k);
+      __builtin_memcpy((char*)x + 16 * k, &u, 16);
+    }
+  } else if constexpr (VIN && NB == 8) {
+    const f2_u32x2 u = gload((const f2_u32x2*)p);
+    __builtin_memcpy(x, &u, 8);
+  } else if constexpr (VIN && NB == 4 && sizeof(T) < 4) {
+    const unsigned u = gload((const unsigned*)p);
+    __builtin_memcpy(x, &u, 4);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) x[i] = gload(p + i);
+  }
+}
+template <class T, int V> __device__ __forceinline__ void f2_store(T* p, const T (&x)[V]) {
+  constexpr int NB = V * (int)sizeof(T);
+  const uintptr_t ad = (uintptr_t)p;
+  if constexpr (NB % 16 == 0) {
+    if (ad % 16 == 0) {
+#pragma unroll
+      for (int k = 0; k < NB / 16; ++k) {
+        f2_u32x4 u;
+        __builtin_memcpy(&u, (const char*)x + 16 * k, 16);
+        gstore((f2_u32x4*)p + k, u);
+      }
+      return;
+    }
+  }
+  if constexpr (NB % 8 == 0) {
+    if (ad % 8 == 0) {
+#pragma unroll
+      for (int k = 0; k < NB / 8; ++k) {
+        f2_u32x2 u;
+        __builtin_memcpy(&u, (const char*)x + 8 * k, 8);
+        gstore((f2_u32x2*)p + k, u);
+      }
+      return;
+    }
+  }
+  if constexpr (NB % 4 == 0 && sizeof(T) < 4) {
+    if (ad % 4 == 0) {
+#pragma unroll
+      for (int k = 0; k < NB / 4; ++k) {
+        unsigned u;
+        __builtin_memcpy(&u, (const char*)x + 4 * k, 4);
+        gstore((unsigned*)p + k, u);
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) gstore(p + i, x[i]);
+}
+
+// Loads of input row `row` for this lane: its V strip columns, and its V
+// halo columns one strip width further (only the first wc-1 halo columns
+// are read; the other lanes load lane 0's halo vector, one cache line).
+// No lane-dependent branch: a branch whose sides write the load's
+// registers would make every lane wait for the load; strips that reach the
+// row end (a wave-uniform test) clamp each column instead.
+// Column-only mode: the V columns of row `row` of the row-filtered images
+// the call needs (max image into x, min image into h), clamped at the row
+// end like the above.
+template <class T, int V, bool VIN, int OUT>
+__device__ __forceinline__ void f2_pair_load(const F2dArgs<T>& a, int64_t row, int64_t c0, T (&x)[V], T (&h)[V]) {
+  const int lane = threadIdx.x & 63;
+  const T* px = a.in + row * a.ld_in;
+  const T* pn = a.in2 + row * a.ld_in;
+  const int64_t cm = c0 + lane * V;
+  if (c0 + 64 * V <= a.cols) {
+    if constexpr ((OUT & 1) != 0) f2_load<T, V, VIN>(px + cm, x);
+    if constexpr ((OUT & 2) != 0) f2_load<T, V, VIN>(pn + cm, h);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if constexpr ((OUT & 1) != 0) x[i] = gload(px + min(cm + i, a.cols - 1));
+      if constexpr ((OUT & 2) != 0) h[i] = gload(pn + min(cm + i, a.cols - 1));
+    }
+  }
+}
+
+template <class T, int V, bool VIN>
+__device__ __forceinline__ void f2_row_load(const F2dArgs<T>& a, int64_t row, int64_t c0, T (&x)[V], T (&h)[V]) {
+  constexpr int W = 64 * V;
+  const int lane = threadIdx.x & 63;
+  const T* rp = a.in + row * a.ld_in;
+  const int64_t cm = c0 + lane * V, chh = c0 + W + (lane * V < a.wc - 1 ? lane * V : 0);
+  if (c0 + 2 * W <= a.cols) {
+    f2_load<T, V, VIN>(rp + cm, x);
+    f2_load<T, V, VIN>(rp + chh, h);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      x[i] = gload(rp + min(cm + i, a.cols - 1));
+      h[i] = gload(rp + min(chh + i, a.cols - 1));
+    }
+  }
+}
+
+// Inclusive scans of (max, min) over aligned groups of m lanes, m a power
+// of two in 2..16 (inside one DPP row).  A step of distance d must not
+// reach into the previous (next) group: that happens exactly where the
+// SOURCE lane has lig >= m - d (lig < d), so the source is masked to the
+// identity there and every lane combines unconditionally -- a select on
+// the DPP source, which the compiler keeps as one v_cndmask (a select on
+// the result it turns into exec-masked branches).
+template <class T, int D> __device__ __forceinline__ void f2_pre_step(T& x, T& n, int m, int lig) {
+  const bool k = lig >= m - D;
+  x = hmax(x, dpp<0x110 + D>(Lim<T>::lo(), k ? Lim<T>::lo() : x));  // row_shr:D
+  n = hmin(n, dpp<0x110 + D>(Lim<T>::hi(), k ? Lim<T>::hi() : n));
+}
+template <class T, int D> __device__ __forceinline__ void f2_suf_step(T& x, T& n, int lig) {
+  const bool k = lig < D;
+  x = hmax(x, dpp<0x100 + D>(Lim<T>::lo(), k ? Lim<T>::lo() : x));  // row_shl:D
+  n = hmin(n, dpp<0x100 + D>(Lim<T>::hi(), k ? Lim<T>::hi() : n));
+}
+template <class T> __device__ __forceinline__ void f2_seg_pre(T& x, T& n, int m, int lig) {
+  f2_pre_step<T, 1>(x, n, m, lig);
+  if (m > 2) f2_pre_step<T, 2>(x, n, m, lig);
+  if (m > 4) f2_pre_step<T, 4>(x, n, m, lig);
+  if (m > 8) f2_pre_step<T, 8>(x, n, m, lig);
+}
+template <class T> __device__ __forceinline__ void f2_seg_suf(T& x, T& n, int m, int lig) {
+  f2_suf_step<T, 1>(x, n, lig);
+  if (m > 2) f2_suf_step<T, 2>(x, n, lig);
+  if (m > 4) f2_suf_step<T, 4>(x, n, lig);
+  if (m > 8) f2_suf_step<T, 8>(x, n, lig);
+}
+
+// The workgroup is one wavefront, whose LDS accesses execute in order: a
+// wavefront-scope fence keeps the compiler from moving them across, and,
+// unlike a workgroup barrier, does not wait for the row loads in flight.
+__device__ __forceinline__ void f2_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// COLS: column-only mode, the input being the pair of row-filtered images
+// (the second pass of rows-then-columns): the same column filter, no row
+// work, no halo columns.  OUT: 3 both outputs, 1 max only, 2 min only (the
+// other side's LDS, loads and arithmetic are compiled out).
+template <class T, int B, int V, bool VIN, bool COLS, int OUT>
+__global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
+  constexpr bool WX = (OUT & 1) != 0, WN = (OUT & 2) != 0;
+  constexpr int W = 64 * V;                     // output columns per strip
+  constexpr int RB = 2 * B;                     // ring rows
+  constexpr int D = V >= 8 ? 2 : (V >= 4 ? 4 : 8);  // input rows in flight
+  __shared__ T ringx[WX ? RB * W : 1], ringn[WN ? RB * W : 1];  // [slot][i][lane]
+  __shared__ T hpx[WX ? lds_len<T>(2 * W) : 1], hpn[WN ? lds_len<T>(2 * W) : 1];  // row PRE, strip + halo
+  const int lane = threadIdx.x;
+  // consecutive tiles on one XCD (workgroups are dealt round robin over
+  // the 8 XCDs), so neighbouring strips share their halo columns in L2
+  const int64_t per = gridDim.x / 8;
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= a.ntiles) return;
+  const int64_t band = tile / a.strips, strip = tile - band * a.strips;
+  const int64_t orows = a.rows - a.wr + 1, oc = a.cols - a.wc + 1;
+  const int64_t c0 = strip * W, r0 = band * (int64_t)a.TR;
+  const int nr = (int)min((int64_t)a.TR, orows - r0);  // output rows of the band
+  const int NR = nr + a.wr - 1;                        // input rows streamed
+  const int wr = a.wr, wc = a.wc;
+  // along the row: blocks of Bh <= 16 V columns, so a block's lanes lie in
+  // one 16-lane DPP row (no cross-row steps); a window then covers up to
+  // kmax whole blocks, whose aggregates are PRE at their last columns
+  const int lgBh = 31 - __builtin_clz((unsigned)min(wc, 16 * V));
+  const int Bh = 1 << lgBh;
+  const int mh = Bh > V ? Bh / V : 1;  // lanes per block, <= 16
+  const int lig = lane & (mh - 1);
+  const int kmax = max(0, (wc + Bh - 2) / Bh - 1);
+  // down the columns: blocks of B rows (wr <= 2B)
+  constexpr int lgB = B == 1 ? 0 : (B == 2 ? 1 : (B == 4 ? 2 : (B == 8 ? 3 : (B == 16 ? 4 : 5))));
+  const bool ovec = c0 + lane * V + V <= oc;  // all V outputs of the lane exist
+
+  T bx[D][V], bh[D][V];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (d < NR) {
+      if constexpr (COLS) f2_pair_load<T, V, VIN, OUT>(a, r0 + d, c0, bx[d], bh[d]);
+      else f2_row_load<T, V, VIN>(a, r0 + d, c0, bx[d], bh[d]);
+    }
+  T Px[V], Pn[V], Ax[V], An[V];  // running column PRE; aggregate of the last whole block
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    Px[i] = Ax[i] = Lim<T>::lo();
+    Pn[i] = An[i] = Lim<T>::hi();
+  }
+  for (int t0 = 0; t0 < NR; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int t = t0 + d;
+      if (t < NR) {
+        T rx[V], rn[V];  // the row-filtered values of this lane's columns
+        if constexpr (COLS) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            rx[i] = bx[d][i];
+            rn[i] = bh[d][i];
+          }
+          if (t + D < NR) f2_pair_load<T, V, VIN, OUT>(a, r0 + t + D, c0, bx[d], bh[d]);
+        } else {
+        // ---- along the row
+        T px[V], pn[V], qx[V], qn[V], sx[V], sn[V];
+        px[0] = pn[0] = bx[d][0];
+        qx[0] = qn[0] = bh[d][0];
+#pragma unroll
+        for (int i = 1; i < V; ++i) {
+          // hmax / hmin are inline asm, which the compiler never moves into
+          // a branch: take them unconditionally, then select (no branches)
+          const bool st = ((lane * V + i) & (Bh - 1)) == 0;  // same phase in the halo (W % Bh == 0)
+          const T ax = hmax(px[i - 1], bx[d][i]), an = hmin(pn[i - 1], bx[d][i]);
+          const T bxx = hmax(qx[i - 1], bh[d][i]), bnn = hmin(qn[i - 1], bh[d][i]);
+          px[i] = st ? bx[d][i] : ax;
+          pn[i] = st ? bx[d][i] : an;
+          qx[i] = st ? bh[d][i] : bxx;
+          qn[i] = st ? bh[d][i] : bnn;
+        }
+        sx[V - 1] = sn[V - 1] = bx[d][V - 1];
+#pragma unroll
+        for (int i = V - 2; i >= 0; --i) {
+          const bool en = ((lane * V + i + 1) & (Bh - 1)) == 0;
+          const T ax = hmax(sx[i + 1], bx[d][i]), an = hmin(sn[i + 1], bx[d][i]);
+          sx[i] = en ? bx[d][i] : ax;
+          sn[i] = en ? bx[d][i] : an;
+        }
+        if (mh > 1) {
+          // lane totals scanned over the block's lanes; each lane then takes
+          // the scan of the lane before (PRE) or after (SUF) it in its block
+          T ix = px[V - 1], in = pn[V - 1], jx = qx[V - 1], jn = qn[V - 1], kx = sx[0], kn = sn[0];
+          f2_seg_pre(ix, in, mh, lig);
+          f2_seg_pre(jx, jn, mh, lig);
+          f2_seg_suf(kx, kn, mh, lig);
+          // (the source lane masked as in the scans: the last lane of a
+          // group passes nothing on to the next, the first nothing back)
+          const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
+          const bool lp = lig == mh - 1, ls = lig == 0;
+          const T cx = dpp<0x111>(lo, lp ? lo : ix), cn = dpp<0x111>(hi, lp ? hi : in);  // row_shr:1
+          const T dx = dpp<0x111>(lo, lp ? lo : jx), dn = dpp<0x111>(hi, lp ? hi : jn);
+          const T ex = dpp<0x101>(lo, ls ? lo : kx), en = dpp<0x101>(hi, ls ? hi : kn);  // row_shl:1
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            px[i] = hmax(px[i], cx);
+            pn[i] = hmin(pn[i], cn);
+            qx[i] = hmax(qx[i], dx);
+            qn[i] = hmin(qn[i], dn);
+            sx[i] = hmax(sx[i], ex);
+            sn[i] = hmin(sn[i], en);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          if constexpr (WX) {
+            hpx[lds_idx<T>(lane * V + i)] = px[i];
+            hpx[lds_idx<T>(W + lane * V + i)] = qx[i];
+          }
+          if constexpr (WN) {
+            hpn[lds_idx<T>(lane * V + i)] = pn[i];
+            hpn[lds_idx<T>(W + lane * V + i)] = qn[i];
+          }
+        }
+        f2_wave_sync();
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const int cc = lane * V + i, e = cc + wc - 1, b1 = cc >> lgBh;
+          if constexpr (WX) rx[i] = hmax(sx[i], hpx[lds_idx<T>(e)]);
+          if constexpr (WN) rn[i] = hmin(sn[i], hpn[lds_idx<T>(e)]);
+          // whole blocks b1+1 .. inside the window; past the last one the
+          // index clamps to e, whose PRE is already taken
+          for (int k = 1; k <= kmax; ++k) {
+            const int mi = min((((b1 + k + 1) << lgBh) - 1), e);
+            if constexpr (WX) rx[i] = hmax(rx[i], hpx[lds_idx<T>(mi)]);
+            if constexpr (WN) rn[i] = hmin(rn[i], hpn[lds_idx<T>(mi)]);
+          }
+        }
+        f2_wave_sync();  // the row buffer is rewritten by the next row
+        // the next loads into this slot of the row queue
+        if (t + D < NR) f2_row_load<T, V, VIN>(a, r0 + t + D, c0, bx[d], bh[d]);
+        }
+        // ---- down the columns
+        const int slot = t & (RB - 1);
+        if ((t & (B - 1)) == 0 && t > 0) {
+          // the block before this row is complete: its suffixes, in place
+          const int s0 = (t - B) & (RB - 1);
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            if constexpr (WX) {
+              T ux = ringx[((s0 + B - 1) * V + i) * 64 + lane];
+              for (int k = B - 2; k >= 0; --k) {
+                const int ix = ((s0 + k) * V + i) * 64 + lane;
+                ux = hmax(ux, ringx[ix]);
+                ringx[ix] = ux;
+              }
+              Ax[i] = ux;
+            }
+            if constexpr (WN) {
+              T un = ringn[((s0 + B - 1) * V + i) * 64 + lane];
+              for (int k = B - 2; k >= 0; --k) {
+                const int ix = ((s0 + k) * V + i) * 64 + lane;
+                un = hmin(un, ringn[ix]);
+                ringn[ix] = un;
+              }
+              An[i] = un;
+            }
+          }
+        }
+        const bool bstart = (t & (B - 1)) == 0;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          if constexpr (WX) ringx[(slot * V + i) * 64 + lane] = rx[i];
+          if constexpr (WN) ringn[(slot * V + i) * 64 + lane] = rn[i];
+          const T ax = hmax(Px[i], rx[i]), an = hmin(Pn[i], rn[i]);
+          Px[i] = bstart ? rx[i] : ax;
+          Pn[i] = bstart ? rn[i] : an;
+        }
+        if (t >= wr - 1) {
+          // the window of rows [j, t] is complete
+          const int j = t - wr + 1, bj = j >> lgB, bt = t >> lgB;
+          const int js = j & (RB - 1);
+          T ox[V], on[V];
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            ox[i] = Px[i];
+            on[i] = Pn[i];
+            if (bt > bj) {
+              if constexpr (WX) ox[i] = hmax(ox[i], ringx[(js * V + i) * 64 + lane]);
+              if constexpr (WN) on[i] = hmin(on[i], ringn[(js * V + i) * 64 + lane]);
+            }
+            if (bt > bj + 1) {
+              ox[i] = hmax(ox[i], Ax[i]);
+              on[i] = hmin(on[i], An[i]);
+            }
+          }
+          const int64_t cm = c0 + lane * V, orow = r0 + j;
+          if (ovec) {
+            if constexpr (WX) f2_store<T, V>(a.omax + orow * a.ld_out + cm, ox);
+            if constexpr (WN) f2_store<T, V>(a.omin + orow * a.ld_out + cm, on);
+          } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+              if (cm + i < oc) {
+                if constexpr (WX) gstore(a.omax + orow * a.ld_out + cm + i, ox[i]);
+                if constexpr (WN) gstore(a.omin + orow * a.ld_out + cm + i, on[i]);
+              }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Column blocks B (largest power of two <= w_rows, at most 32) and lane
+// widths V: the ring is 2B x 64V elements per image per wavefront, so V
+// trades the per-column cost of the row scans against LDS occupancy.  On
+// MI355X (8192^2 float32 / uint16, w = 3 and 15) V = 4 (B <= 4), 2 (B = 8)
+// and 1 beat twice those widths by 10-40% and half of them by up to 30%.
+inline int f2d_V(int B, size_t) { return B >= 16 ? 1 : (B >= 8 ? 2 : 4); }
+inline size_t f2d_size(int dtype) { return dtype == 1 ? 8 : (dtype == 3 ? 2 : 4); }
+
+
+template <class T, int B, int V, bool COLS, int OUT>
+hipError_t f2d_go(const F2dArgs<T>& a, int64_t grid, hipStream_t st) {
+  const size_t al = std::min<size_t>(16, (size_t)V * sizeof(T));
+  const bool vin = al >= 4 && (uintptr_t)a.in % al == 0 && (uintptr_t)a.in2 % al == 0 &&
+                   ((size_t)a.ld_in * sizeof(T)) % al == 0;
+  if (vin) hipLaunchKernelGGL((k_f2d<T, B, V, true, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
+  else hipLaunchKernelGGL((k_f2d<T, B, V, false, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+// Shared launcher: COLS = column-only mode (in, in2: the row-filtered max
+// and min images, w_cols = 1); OUT as in k_f2d.  Instantiated in one
+// translation unit per OUT (compiled in parallel).
+template <bool COLS, int OUT>
+hipError_t f2d_launch(int dtype, const void* d_in, const void* d_in2, int64_t ld_in, int64_t rows,
+                             int64_t cols, int64_t w_rows, int64_t w_cols, void* d_max, void* d_min, int64_t ld_out,
+                             int64_t band_rows, hipStream_t st) {
+  const int64_t orows = rows - w_rows + 1, oc = cols - w_cols + 1;
+  if (orows <= 0 || oc <= 0) return hipSuccess;
+  int B = 1;
+  while (2 * B <= w_rows) B *= 2;
+  const int V = f2d_V(B, f2d_size(dtype)), W = 64 * V;
+  const int64_t strips = (oc + W - 1) / W;
+  // bands: about four waves per SIMD over the chip when the image allows,
+  // at least 4B rows each so the w_rows-1 halo rows stay a small share
+  int64_t TR = band_rows;
+  if (TR <= 0) {
+    const int64_t target = 4 * 4 * 256;
+    const int64_t bands = std::max<int64_t>(1, target / strips);
+    TR = std::max<int64_t>((orows + bands - 1) / bands, 4 * B);
+  }
+  TR = std::min<int64_t>(TR, orows);
+  if (TR > (1 << 30)) return hipErrorNotSupported;
+  const int64_t bands = (orows + TR - 1) / TR;
+  const int64_t ntiles = strips * bands;
+  const int64_t grid = (ntiles + 7) / 8 * 8;
+  if (grid > 0x7fffffff) return hipErrorNotSupported;
+  auto go = [&](auto* p) -> hipError_t {
+    using T = std::remove_pointer_t<decltype(p)>;
+    F2dArgs<T> a;
+    a.in = (const T*)d_in;
+    a.in2 = (const T*)d_in2;
+    a.ld_in = ld_in;
+    a.rows = rows;
+    a.cols = cols;
+    a.wr = (int)w_rows;
+    a.wc = (int)w_cols;
+    a.omax = (T*)d_max;
+    a.omin = (T*)d_min;
+    a.ld_out = ld_out;
+    a.strips = (int)strips;
+    a.TR = (int)TR;
+    a.ntiles = ntiles;
+    switch (B) {
+      case 1: return f2d_go<T, 1, 4, COLS, OUT>(a, grid, st);
+      case 2: return f2d_go<T, 2, 4, COLS, OUT>(a, grid, st);
+      case 4: return f2d_go<T, 4, 4, COLS, OUT>(a, grid, st);
+      case 8: return f2d_go<T, 8, 2, COLS, OUT>(a, grid, st);
+      case 16: return f2d_go<T, 16, 1, COLS, OUT>(a, grid, st);
+      default: return f2d_go<T, 32, 1, COLS, OUT>(a, grid, st);
+    }
+  };
+  switch (dtype) {
+    case 0: return go((float*)nullptr);
+    case 1: return go((double*)nullptr);
+    case 2: return go((int32_t*)nullptr);
+    case 3: return go((uint16_t*)nullptr);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+
+// one translation unit each
+extern template hipError_t f2d_launch<false, 1>(int, const void*, const void*, int64_t, int64_t, int64_t, int64_t,
+                                                int64_t, void*, void*, int64_t, int64_t, hipStream_t);
+extern template hipError_t f2d_launch<true, 1>(int, const void*, const void*, int64_t, int64_t, int64_t, int64_t,
+                                               int64_t, void*, void*, int64_t, int64_t, hipStream_t);
+extern template hipError_t f2d_launch<false, 2>(int, const void*, const void*, int64_t, int64_t, int64_t, int64_t,
+                                                int64_t, void*, void*, int64_t, int64_t, hipStream_t);
+extern template hipError_t f2d_launch<true, 2>(int, const void*, const void*, int64_t, int64_t, int64_t, int64_t,
+                                               int64_t, void*, void*, int64_t, int64_t, hipStream_t);
+extern template hipError_t f2d_launch<false, 3>(int, const void*, const void*, int64_t, int64_t, int64_t, int64_t,
+                                                int64_t, void*, void*, int64_t, int64_t, hipStream_t);
+extern template hipError_t f2d_launch<true, 3>(int, const void*, const void*, int64_t, int64_t, int64_t, int64_t,
+                                               int64_t, void*, void*, int64_t, int64_t, hipStream_t);
+
+}  // namespace mm

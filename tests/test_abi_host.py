@@ -111,12 +111,17 @@ def test_planner_2d(lib, monkeypatch):
         assert binding.maxmin_plan_2d(dt, 31, 65) == big
         assert binding.maxmin_plan_2d(dt, 32, 3) == RC and binding.maxmin_plan_2d(dt, 63, 63) == RC
         assert binding.maxmin_plan_2d(dt, 65, 1) == RC
+        # one output: the fused pass up to w_rows 31 for every type
+        assert binding.maxmin_plan_2d(dt, 31, 65, outputs=1) == F
+        assert binding.maxmin_plan_2d(dt, 32, 3, outputs=1) == RC
     monkeypatch.setenv("MAXMIN_2D_FUSED", "1")
     assert binding.maxmin_plan_2d(np.float32, 63, 63) == F
     monkeypatch.setenv("MAXMIN_2D_FUSED", "0")
     assert binding.maxmin_plan_2d(np.float32, 3, 3) == RC
     with pytest.raises(binding.MaxMinError):
         binding.maxmin_plan_2d(np.float32, 0, 3)
+    with pytest.raises(binding.MaxMinError):
+        binding.maxmin_plan_2d(np.float32, 3, 3, outputs=3)
 
 
 def test_planner(lib):
