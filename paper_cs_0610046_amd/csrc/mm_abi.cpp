@@ -150,7 +150,7 @@ struct Workspace {
   uint32_t ring_lg = 0;
   void* descs = nullptr;
   int64_t desc_cap = 0;
-  int64_t* pre = nullptr;  // 2 * pre_cap int64
+  int64_t* pre = nullptr;  // 2 * pre_cap + 2 * kBatchMaxGroups + 2 int64
   int64_t pre_cap = 0;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
@@ -255,7 +255,9 @@ int ensure_batch(Workspace* ws, int64_t S) {
   ws->pre = nullptr;
   const int64_t cap = std::max<int64_t>(S, 1024);
   hipError_t e = hipMalloc(&ws->descs, (size_t)cap * mm::series_bytes());
-  if (e == hipSuccess) e = hipMalloc((void**)&ws->pre, (size_t)2 * (cap + 1) * sizeof(int64_t));
+  // two prefix arrays of cap + 1, then the setup's per-workgroup totals
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&ws->pre, (size_t)(2 * (cap + 1) + 2 * mm::kBatchMaxGroups + 2) * sizeof(int64_t));
   if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(batched descriptors): %s", hipGetErrorString(e));
   ws->desc_cap = cap;
   ws->pre_cap = cap + 1;

@@ -187,6 +187,94 @@ __device__ __forceinline__ void f2_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One row filtered along the row: x holds this lane's V positions of a
+// row segment, h its V positions one segment width (64 V) further (only
+// positions < 64 V + wc - 1 are read); rx / rn get max / min over
+// [p, p + wc - 1] for the lane's positions p.  Blocks of Bh = 2^lgBh <= 16 V
+// positions, mh = max(1, Bh / V) lanes each (lig = lane & (mh - 1)); kmax
+// whole blocks at most inside a window.  hpx / hpn: this wavefront's LDS row
+// buffer of lds_len<T>(128 V) elements (only the side WX / WN is used).
+// The caller orders the buffer's next reuse (f2_wave_sync).
+template <class T, int V, bool WX, bool WN>
+__device__ __forceinline__ void f2_row_filter(const T (&x)[V], const T (&h)[V], int wc, int lgBh, int mh, int lig,
+                                              int kmax, T* hpx, T* hpn, T (&rx)[V], T (&rn)[V]) {
+  constexpr int W = 64 * V;
+  const int lane = threadIdx.x & 63;
+  const int Bh = 1 << lgBh;
+  T px[V], pn[V], qx[V], qn[V], sx[V], sn[V];
+  px[0] = pn[0] = x[0];
+  qx[0] = qn[0] = h[0];
+#pragma unroll
+  for (int i = 1; i < V; ++i) {
+    // hmax / hmin are inline asm, which the compiler never moves into
+    // a branch: take them unconditionally, then select (no branches)
+    const bool st = ((lane * V + i) & (Bh - 1)) == 0;  // same phase in the halo (W % Bh == 0)
+    const T ax = hmax(px[i - 1], x[i]), an = hmin(pn[i - 1], x[i]);
+    const T bxx = hmax(qx[i - 1], h[i]), bnn = hmin(qn[i - 1], h[i]);
+    px[i] = st ? x[i] : ax;
+    pn[i] = st ? x[i] : an;
+    qx[i] = st ? h[i] : bxx;
+    qn[i] = st ? h[i] : bnn;
+  }
+  sx[V - 1] = sn[V - 1] = x[V - 1];
+#pragma unroll
+  for (int i = V - 2; i >= 0; --i) {
+    const bool en = ((lane * V + i + 1) & (Bh - 1)) == 0;
+    const T ax = hmax(sx[i + 1], x[i]), an = hmin(sn[i + 1], x[i]);
+    sx[i] = en ? x[i] : ax;
+    sn[i] = en ? x[i] : an;
+  }
+  if (mh > 1) {
+    // lane totals scanned over the block's lanes; each lane then takes
+    // the scan of the lane before (PRE) or after (SUF) it in its block
+    T ix = px[V - 1], in = pn[V - 1], jx = qx[V - 1], jn = qn[V - 1], kx = sx[0], kn = sn[0];
+    f2_seg_pre(ix, in, mh, lig);
+    f2_seg_pre(jx, jn, mh, lig);
+    f2_seg_suf(kx, kn, mh, lig);
+    // (the source lane masked as in the scans: the last lane of a
+    // group passes nothing on to the next, the first nothing back)
+    const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
+    const bool lp = lig == mh - 1, ls = lig == 0;
+    const T cx = dpp<0x111>(lo, lp ? lo : ix), cn = dpp<0x111>(hi, lp ? hi : in);  // row_shr:1
+    const T dx = dpp<0x111>(lo, lp ? lo : jx), dn = dpp<0x111>(hi, lp ? hi : jn);
+    const T ex = dpp<0x101>(lo, ls ? lo : kx), en = dpp<0x101>(hi, ls ? hi : kn);  // row_shl:1
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      px[i] = hmax(px[i], cx);
+      pn[i] = hmin(pn[i], cn);
+      qx[i] = hmax(qx[i], dx);
+      qn[i] = hmin(qn[i], dn);
+      sx[i] = hmax(sx[i], ex);
+      sn[i] = hmin(sn[i], en);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    if constexpr (WX) {
+      hpx[lds_idx<T>(lane * V + i)] = px[i];
+      hpx[lds_idx<T>(W + lane * V + i)] = qx[i];
+    }
+    if constexpr (WN) {
+      hpn[lds_idx<T>(lane * V + i)] = pn[i];
+      hpn[lds_idx<T>(W + lane * V + i)] = qn[i];
+    }
+  }
+  f2_wave_sync();
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int cc = lane * V + i, e = cc + wc - 1, b1 = cc >> lgBh;
+    if constexpr (WX) rx[i] = hmax(sx[i], hpx[lds_idx<T>(e)]);
+    if constexpr (WN) rn[i] = hmin(sn[i], hpn[lds_idx<T>(e)]);
+    // whole blocks b1+1 .. inside the window; past the last one the
+    // index clamps to e, whose PRE is already taken
+    for (int k = 1; k <= kmax; ++k) {
+      const int mi = min((((b1 + k + 1) << lgBh) - 1), e);
+      if constexpr (WX) rx[i] = hmax(rx[i], hpx[lds_idx<T>(mi)]);
+      if constexpr (WN) rn[i] = hmin(rn[i], hpn[lds_idx<T>(mi)]);
+    }
+  }
+}
+
 // COLS: column-only mode, the input being the pair of row-filtered images
 // (the second pass of rows-then-columns): the same column filter, no row
 // work, no halo columns.  OUT: 3 both outputs, 1 max only, 2 min only (the
@@ -251,78 +339,7 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<T> a) {
           if (t + D < NR) f2_pair_load<T, V, VIN, OUT>(a, r0 + t + D, c0, bx[d], bh[d]);
         } else {
         // ---- along the row
-        T px[V], pn[V], qx[V], qn[V], sx[V], sn[V];
-        px[0] = pn[0] = bx[d][0];
-        qx[0] = qn[0] = bh[d][0];
-#pragma unroll
-        for (int i = 1; i < V; ++i) {
-          // hmax / hmin are inline asm, which the compiler never moves into
-          // a branch: take them unconditionally, then select (no branches)
-          const bool st = ((lane * V + i) & (Bh - 1)) == 0;  // same phase in the halo (W % Bh == 0)
-          const T ax = hmax(px[i - 1], bx[d][i]), an = hmin(pn[i - 1], bx[d][i]);
-          const T bxx = hmax(qx[i - 1], bh[d][i]), bnn = hmin(qn[i - 1], bh[d][i]);
-          px[i] = st ? bx[d][i] : ax;
-          pn[i] = st ? bx[d][i] : an;
-          qx[i] = st ? bh[d][i] : bxx;
-          qn[i] = st ? bh[d][i] : bnn;
-        }
-        sx[V - 1] = sn[V - 1] = bx[d][V - 1];
-#pragma unroll
-        for (int i = V - 2; i >= 0; --i) {
-          const bool en = ((lane * V + i + 1) & (Bh - 1)) == 0;
-          const T ax = hmax(sx[i + 1], bx[d][i]), an = hmin(sn[i + 1], bx[d][i]);
-          sx[i] = en ? bx[d][i] : ax;
-          sn[i] = en ? bx[d][i] : an;
-        }
-        if (mh > 1) {
-          // lane totals scanned over the block's lanes; each lane then takes
-          // the scan of the lane before (PRE) or after (SUF) it in its block
-          T ix = px[V - 1], in = pn[V - 1], jx = qx[V - 1], jn = qn[V - 1], kx = sx[0], kn = sn[0];
-          f2_seg_pre(ix, in, mh, lig);
-          f2_seg_pre(jx, jn, mh, lig);
-          f2_seg_suf(kx, kn, mh, lig);
-          // (the source lane masked as in the scans: the last lane of a
-          // group passes nothing on to the next, the first nothing back)
-          const T lo = Lim<T>::lo(), hi = Lim<T>::hi();
-          const bool lp = lig == mh - 1, ls = lig == 0;
-          const T cx = dpp<0x111>(lo, lp ? lo : ix), cn = dpp<0x111>(hi, lp ? hi : in);  // row_shr:1
-          const T dx = dpp<0x111>(lo, lp ? lo : jx), dn = dpp<0x111>(hi, lp ? hi : jn);
-          const T ex = dpp<0x101>(lo, ls ? lo : kx), en = dpp<0x101>(hi, ls ? hi : kn);  // row_shl:1
-#pragma unroll
-          for (int i = 0; i < V; ++i) {
-            px[i] = hmax(px[i], cx);
-            pn[i] = hmin(pn[i], cn);
-            qx[i] = hmax(qx[i], dx);
-            qn[i] = hmin(qn[i], dn);
-            sx[i] = hmax(sx[i], ex);
-            sn[i] = hmin(sn[i], en);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          if constexpr (WX) {
-            hpx[lds_idx<T>(lane * V + i)] = px[i];
-            hpx[lds_idx<T>(W + lane * V + i)] = qx[i];
-          }
-          if constexpr (WN) {
-            hpn[lds_idx<T>(lane * V + i)] = pn[i];
-            hpn[lds_idx<T>(W + lane * V + i)] = qn[i];
-          }
-        }
-        f2_wave_sync();
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          const int cc = lane * V + i, e = cc + wc - 1, b1 = cc >> lgBh;
-          if constexpr (WX) rx[i] = hmax(sx[i], hpx[lds_idx<T>(e)]);
-          if constexpr (WN) rn[i] = hmin(sn[i], hpn[lds_idx<T>(e)]);
-          // whole blocks b1+1 .. inside the window; past the last one the
-          // index clamps to e, whose PRE is already taken
-          for (int k = 1; k <= kmax; ++k) {
-            const int mi = min((((b1 + k + 1) << lgBh) - 1), e);
-            if constexpr (WX) rx[i] = hmax(rx[i], hpx[lds_idx<T>(mi)]);
-            if constexpr (WN) rn[i] = hmin(rn[i], hpn[lds_idx<T>(mi)]);
-          }
-        }
+        f2_row_filter<T, V, WX, WN>(bx[d], bh[d], wc, lgBh, mh, lig, kmax, hpx, hpn, rx, rn);
         f2_wave_sync();  // the row buffer is rewritten by the next row
         // the next loads into this slot of the row queue
         if (t + D < NR) f2_row_load<T, V, VIN>(a, r0 + t + D, c0, bx[d], bh[d]);

@@ -45,6 +45,15 @@ __host__ __device__ inline int64_t crun_chunks(int64_t n, int64_t w) {
 // Batched strategy selection happens on the device with the same rule as the
 // host planner's default: tile for w <= kTileMaxW, chunk otherwise.
 
+// Batched envelopes: a series of at most kEnvShortN samples with radius at
+// most kEnvShortR is served whole by one wavefront (k_env_short); the others
+// by the batched filter plus the end scans.  Decided on the device.
+constexpr int64_t kEnvShortN = 16384;
+constexpr int64_t kEnvShortR = 256;  // window 2r+1 <= 513 = one 512-position segment + 1
+__host__ __device__ inline bool env_short(int64_t n, int64_t r) {
+  return n > 0 && n <= kEnvShortN && r >= 0 && r <= kEnvShortR;
+}
+
 // Runs of `run` windows covering the n - w + 1 windows of a series.
 __host__ __device__ inline int64_t run_count(int64_t n, int64_t w, int64_t run) {
   int64_t no = n - w + 1;
@@ -110,8 +119,11 @@ int grid_cap(int dtype, int strategy);
 
 hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st);
 
-// Batched: one workgroup fills S descriptors (bytes: S * series_bytes())
-// and the per-strategy tile prefix sums pre_tile/pre_chunk (S+1 each).
+// Batched setup: fills S descriptors (bytes: S * series_bytes()) and the
+// per-strategy tile prefix sums pre_tile / pre_chunk (S + 1 entries each);
+// the 2 * kBatchMaxGroups + 2 entries after pre_chunk[S] are scratch for
+// the per-workgroup totals.
+constexpr int64_t kBatchMaxGroups = 1024;
 hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
                                 const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
                                 int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st, int64_t run = kRunBatched);
@@ -125,6 +137,9 @@ hipError_t launch_carry_only(int dtype, const JobArgs& a, hipStream_t st);
 hipError_t launch_env_ends(int dtype, const void* a, int64_t n, int64_t r, void* up, void* lo, hipStream_t st);
 hipError_t launch_env_batched(int dtype, const void* in, const int64_t* off, const int64_t* radii, int64_t S,
                               int64_t* wins, int64_t* oo, bool setup, void* up, void* lo, hipStream_t st);
+// The short series of a batched envelope call (env_short), one wavefront each.
+hipError_t launch_env_short(int dtype, const void* in, const int64_t* off, const int64_t* radii, int64_t S, void* up,
+                            void* lo, hipStream_t st);
 // One step of the arg filter's long-window path (see k_argcombine): window
 // p's outputs j < nout from F reads of window q's value/location arrays.
 hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,

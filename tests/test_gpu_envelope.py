@@ -99,3 +99,30 @@ def test_envelope_batched():
             mm.maxmin_check_stream()
             assert_bits_equal(to_host(up, dt), eu, "batched upper rep %d" % rep)
             assert_bits_equal(to_host(lo, dt), el, "batched lower rep %d" % rep)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32, np.uint16], ids=lambda d: np.dtype(d).name)
+def test_envelope_batched_short_and_long(dt):
+    """Series served whole by one wavefront (n <= 16384, r <= 256) mixed with
+    series that take the batched filter plus end scans (longer, or wider
+    radius): lengths at the 512-output segment edges and the short limit,
+    radius 0, radius at the limit, radius past the series, single samples,
+    empty series."""
+    import torch
+    rng = synth.rng_for("tests", 703)
+    lens = [1, 2, 511, 512, 513, 1024, 1500, 16384, 16385, 20000, 0, 3, 777, 4096, 16384, 9000, 300, 1]
+    radii = [0, 0, 3, 256, 255, 100, 257, 256, 10, 256, 5, 2, 777, 1000, 0, 300, 150, 400]
+    lens += list(rng.integers(1, 3000, 40))
+    radii += list(rng.integers(0, 400, 40))
+    lens, radii = np.array(lens, np.int64), np.array(radii, np.int64)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    packed = _gen(int(offs[-1]), dt, rng)
+    d_off, d_r = torch.from_numpy(offs).cuda(), torch.from_numpy(radii).cuda()
+    x = to_dev(packed)
+    note("envelope batched short/long dt=%s" % np.dtype(dt).name)
+    eu, el = oracle.envelope_batched(packed, offs, radii)
+    up, lo = mm.maxmin_envelope_batched(x, d_off, d_r)
+    torch.cuda.synchronize()
+    mm.maxmin_check_stream()
+    assert_bits_equal(to_host(up, dt), eu, "short/long upper")
+    assert_bits_equal(to_host(lo, dt), el, "short/long lower")
