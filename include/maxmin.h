@@ -81,9 +81,11 @@ int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max
  * location of the window's max, and of its min.
  *   d_argmax, d_argmin : n_out int64 each, 0-based positions in d_in.
  * w <= 4096 runs the tile kernel with (value, location) pairs; longer
- * windows add combine steps (window p as the union of F <= 16 overlapping
- * windows of ceil(p/F)) through library scratch of up to 2 x n x (2 s + 16)
- * bytes, grown outside graph capture (EBUSY inside one).
+ * windows start from it at a window q <= 4096 and then either take one
+ * running window over rows of q level entries (8192 < w <= 31 x 4096) or
+ * combine steps (window p as the union of F <= 16 overlapping windows of
+ * ceil(p/F)), through library scratch of up to 2 x n x (2 s + 16) bytes,
+ * grown outside graph capture (EBUSY inside one).
  * Errors: EINVAL if w < 1, n < 0, or a pointer is null or misaligned while
  * n_out > 0; ENOMEM if the scratch cannot be allocated.
  */

@@ -18,7 +18,7 @@ LIB_NAME = "libmaxmin.so"
 LIB_PATH = os.path.join(OUT_DIR, LIB_NAME)
 
 SOURCES = ["mm_kernels_1d.hip", "mm_kernels_2d.hip", "mm_kernels_2d_max.hip", "mm_kernels_2d_min.hip",
-           "mm_kernels_env.hip", "mm_abi.cpp", "mm_engine.cpp"]
+           "mm_kernels_env.hip", "mm_kernels_arg.hip", "mm_abi.cpp", "mm_engine.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
@@ -38,7 +38,7 @@ def _compile(src):
 def build(verbose=False):
     """Compile every HIP source and link libmaxmin.so (always rebuilds)."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

@@ -424,6 +424,49 @@ int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s) || !aligned(d_argmax, 8) || !aligned(d_argmin, 8))
     return fail(MAXMIN_EINVAL, "maxmin_argfilter: pointer not aligned to the element size");
   hipStream_t st = (hipStream_t)stream;
+  // 2 x 4096 < w <= 31 x 4096: the tile kernel at q = floor(w / F), F =
+  // ceil(w / 4096), then one running window of F rows of q level entries
+  // (each entry read once).  On MI355X (n = 2^28 float32) it beat the
+  // combine steps below from F = 3 on (w = 8193 / 16385 / 65536: 6.1 / 6.3
+  // / 5.3 ms against 6.6 / 8.7 / 13.1 ms) and lost at F = 2 (w = 4097: 6.1
+  // against 5.5 ms).  MAXMIN_ARG_CHAIN=1 forces the combine steps (tests).
+  if (w > 2 * mm::kTileMaxW2) {
+    const int64_t F = (w + mm::kTileMaxW2 - 1) / mm::kTileMaxW2;
+    const char* ec = getenv("MAXMIN_ARG_CHAIN");
+    if (F <= mm::kArgColsMaxF && !(ec && !strcmp(ec, "1"))) {
+      const int64_t q = w / F;
+      const size_t set_bytes = (size_t)n * (2 * s + 2 * sizeof(int64_t));
+      Workspace* ws = nullptr;
+      int r = get_ws(st, &ws);
+      if (r) return r;
+      if ((r = ensure_tmp(ws, set_bytes))) return r;
+      char* lv = (char*)ws->tmp;
+      void* lvx = lv;
+      void* lvn = lv + (size_t)n * s;
+      int64_t* lix = (int64_t*)(lv + (size_t)n * 2 * s);
+      int64_t* lin = lix + n;
+      JobArgs a;
+      a.mode = 0;
+      a.a = d_in;
+      a.na = n;
+      a.n = n;
+      a.w = q;
+      a.omax = lvx;
+      a.omin = lvn;
+      a.amax = lix;
+      a.amin = lin;
+      const int ks = q <= mm::kTileMaxW ? mm::kStratArg : mm::kStratArg2;
+      const int cap = mm::grid_cap(dtype, ks);
+      a.run = mm::run_length(n - q + 1, cap, (ks == mm::kStratArg2 ? 4 : 1) * mm::kTileRunMax);
+      a.ntiles = mm::run_count(n, q, a.run);
+      hipError_t e = mm::launch_1d(dtype, ks, a, (int)std::min<int64_t>(a.ntiles, cap), st);
+      if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter");
+      e = mm::launch_arg_cols(dtype, lvx, lix, lvn, lin, n - q + 1, q, w, n - w + 1, d_max, d_argmax, d_min, d_argmin,
+                              st);
+      if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter (rows of level entries)");
+      return ok();
+    }
+  }
   // windows: w, then ceil(w/F), ... down to the first one the tile kernel
   // takes, with the fewest steps of fan-in F <= 16 (each step reads F
   // shorter windows per output)

@@ -142,6 +142,14 @@ hipError_t launch_env_short(int dtype, const void* in, const int64_t* off, const
                             void* lo, hipStream_t st);
 // One step of the arg filter's long-window path (see k_argcombine): window
 // p's outputs j < nout from F reads of window q's value/location arrays.
+// Long-window arg filter, one step: from the level of window q (values and
+// int64 locations, nlv = n - q + 1 entries each) to window w, F = w / q in
+// 2..kArgColsMaxF rows of q entries plus, if Fq < w, the entry at j+w-q
+// ((F+1)q >= w required).  hipErrorInvalidValue outside those limits.
+constexpr int64_t kArgColsMaxF = 31;
+hipError_t launch_arg_cols(int dtype, const void* vx, const int64_t* ix, const void* vn, const int64_t* in,
+                           int64_t nlv, int64_t q, int64_t w, int64_t nout, void* ox, int64_t* jx, void* on,
+                           int64_t* jn, hipStream_t st);
 hipError_t launch_arg_combine(int dtype, const void* vx, const void* vn, const int64_t* ix, const int64_t* in_,
                               int64_t q, int64_t p, int F, int64_t nout, void* ox, void* on, int64_t* jx, int64_t* jn,
                               hipStream_t st);

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 DTS = [np.float32, np.float64, np.int32, np.uint16]
 WINDOWS = [1, 2, 3, 7, 8, 9, 16, 63, 64, 65, 255, 256, 511, 512, 513, 1000, 1024, 1025, 1500, 2048, 2049,
-           3000, 4095, 4096, 4097, 8193, 10000, 65536, 70000]
+           3000, 4095, 4096, 4097, 6000, 8193, 10000, 65536, 70000, 126976, 126977]
 
 
 def _data(n, dt, rng, ties):
@@ -55,8 +55,17 @@ def _check(a, w, what, off=(0, 0, 0, 0, 0)):
     assert bad.size == 0, "%s argmin: %d mismatches, first at %d: got %d want %d" % (what, bad.size, bad[0], gin[bad[0]], ein[bad[0]])
 
 
+@pytest.fixture(params=["rows", "chain"])
+def argpath(request, monkeypatch):
+    """Windows over 4096: one running window over rows of level entries, or
+    (MAXMIN_ARG_CHAIN=1) the combine steps, which also serve w > 31 x 4096."""
+    if request.param == "chain":
+        monkeypatch.setenv("MAXMIN_ARG_CHAIN", "1")
+    return request.param
+
+
 @pytest.mark.parametrize("dt", DTS, ids=lambda d: np.dtype(d).name)
-def test_argfilter_windows(dt):
+def test_argfilter_windows(dt, argpath):
     rng = synth.rng_for("tests", 500)
     for w in WINDOWS:
         for n in sorted({w, w + 1, 2 * w + 3, 40001, 2048 + w - 1, 4096 * 3 + w + 11}):
