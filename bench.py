@@ -300,7 +300,7 @@ def run_extras(torch, mm, synth, dev, stream):
     # arg filter: n = 2^28 float32 walk, values and leftmost locations
     xa = torch.from_numpy(synth.random_walk(1 << 28, np.float32, synth.rng_for("large", 0))).to(dev)
     res = {}
-    for w in (256, 4096):
+    for w in (256, 4096, 65536):
         outs = mm.maxmin_argfilter(xa, w)
         mm.maxmin_argfilter(xa, w, *outs)
         ts = timed(lambda: mm.maxmin_argfilter(xa, w, *outs), 5, stream)
@@ -308,7 +308,8 @@ def run_extras(torch, mm, synth, dev, stream):
         ab = xa.numel() * 4 + outs[0].numel() * (2 * 4 + 2 * 8)
         res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(xa.numel() / (ms * 1e-3) / 1e9, 2),
                        "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
-                       "path": "tile with locations" if w <= 2048 else "tile + combine steps"}
+                       "path": "tile with locations" if w <= 4096 else
+                       ("tile + combine step" if w <= 8192 else "tile + running window over level rows")}
         del outs
     out["argfilter"] = {"workload": "n=2^28 float32 walk; max, min and their leftmost int64 locations "
                                     "(algorithmic bytes: 4 read + 24 written per window)", "per_window": res}
