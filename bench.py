@@ -342,7 +342,7 @@ def run_extras(torch, mm, synth, dev, stream):
     ms = float(np.median(ts))
     ab = 3 * xe.numel() * 4
     out["envelope"] = {"workload": "100,000 float32 walks of 1024 samples, radius uniform [10, 100], one batched "
-                                   "call (interiors by graph replay + end scans)",
+                                   "call (one wavefront per short series)",
                        "ms": round(ms, 4), "gelem_s": round(xe.numel() / (ms * 1e-3) / 1e9, 2),
                        "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
     del xe, eu, el
