@@ -35,8 +35,18 @@ __global__ __launch_bounds__(256) void k_env_short(const T* in, const int64_t* o
   const int np = W + wc - 1;  // inputs of a segment, <= 2W
   for (int64_t c0 = 0; c0 < n; c0 += W) {
     // lane-consecutive (coalesced) loads into LDS, then V consecutive
-    // positions per lane (series start anywhere: no vector alignment)
-    for (int p = lane; p < np; p += 64) bx[lds_idx<T>(p)] = gload(a + min(max(c0 - r + p, (int64_t)0), n - 1));
+    // positions per lane (series start anywhere: no vector alignment); all
+    // loads are issued before the first is used (a loop storing each load
+    // as it arrives ran 20% slower)
+    T ld[2 * V];
+#pragma unroll
+    for (int u = 0; u < 2 * V; ++u) {
+      const int p = u * 64 + lane;
+      ld[u] = gload(a + min(max(c0 - r + (p < np ? p : 0), (int64_t)0), n - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * V; ++u)
+      if (u * 64 + lane < np) bx[lds_idx<T>(u * 64 + lane)] = ld[u];
     f2_wave_sync();
     T x[V], h[V], rx[V], rn[V];
 #pragma unroll
