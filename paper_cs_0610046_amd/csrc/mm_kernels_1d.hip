@@ -866,8 +866,11 @@ template <int MODE, class T>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   __shared__ ChunkLds<T> sm;
   Ctl* ctl = job.ctl;
-  const uint32_t ep = ld_agent32(&ctl->epoch);
   const int64_t ntiles = job_tiles<MODE>(job);
+  // no chunks (a batch with no long window): touch no control word, so the
+  // next launch finds them as this one did (no records were published)
+  if (ntiles == 0) return;
+  const uint32_t ep = ld_agent32(&ctl->epoch);
   // A single series may split into R contiguous ranges of chunks, each with
   // its own in-order tickets and served by the workgroups with blockIdx % R
   // equal to its number.  Workgroup ids go round robin over the 8 XCDs, so
