@@ -11,6 +11,7 @@
 // Each row access is 64 consecutive elements of one image row (coalesced);
 // loads are issued in batches of 8 rows to keep them in flight.
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "mm_f2d.hpp"
@@ -140,6 +141,106 @@ hipError_t launch_f2d_cols(int dtype, const void* tmax, const void* tmin, int64_
   return f(dtype, a, b, ld_t, rows, oc, w_rows, 1, d_max, d_min, ld_out, band_rows, st);
 }
 
+// The same column pass with each column's block suffixes in registers (4-
+// and 2-byte data, w_rows <= 64): two 32-slot vectors per image, indexed by
+// a wavefront-uniform slot number (indirect register addressing), so no
+// LDS: 183 VGPRs, two wavefronts per SIMD instead of the five per CU that
+// 32 KiB of LDS per wavefront allowed at w_rows = 63.
+typedef unsigned int cr_u32x32 __attribute__((ext_vector_type(32)));
+struct CrRing {
+  cr_u32x32 a, b;
+};
+template <class T> __device__ __forceinline__ uint32_t cr_bits(T v) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, v);
+  else return (uint32_t)__builtin_bit_cast(uint16_t, v);
+}
+template <class T> __device__ __forceinline__ T cr_val(uint32_t b) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, b);
+  else return __builtin_bit_cast(T, (uint16_t)b);
+}
+__device__ __forceinline__ void cr_set(CrRing& r, int i, uint32_t v) {
+  i = __builtin_amdgcn_readfirstlane(i);
+  if (i < 32) r.a[i] = v;
+  else r.b[i - 32] = v;
+}
+__device__ __forceinline__ uint32_t cr_get(const CrRing& r, int i) {
+  i = __builtin_amdgcn_readfirstlane(i);
+  return i < 32 ? r.a[i] : r.b[i - 32];
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_cols_reg(const T* __restrict__ M, const T* __restrict__ N, int64_t ld_t,
+                                                 int64_t rows, int64_t oc, int64_t w, T* __restrict__ omax,
+                                                 T* __restrict__ omin, int64_t ld_out) {
+  static_assert(sizeof(T) <= 4, "32-bit register slots");
+  const int lane = threadIdx.x;
+  const bool hx = M != nullptr, hn = N != nullptr;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+  const bool act = c < oc;
+  const int64_t cc = act ? c : 0;
+  const int64_t orows = rows - w + 1;
+  const int64_t r0 = (int64_t)blockIdx.y * w;  // first output row of the block
+  if (r0 >= orows) return;
+  const int64_t nb = min(w, orows - r0);  // outputs of this block
+  CrRing Sx, Sn;
+  // own block rows [r0, r0+w), bottom-up: suffix max/min
+  T sx = Lim<T>::lo(), sn = Lim<T>::hi();
+  for (int64_t i0 = w - 1; i0 >= 0; i0 -= kColBatch) {
+    T vx[kColBatch], vn[kColBatch];
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 - u;
+      vx[u] = Lim<T>::lo();
+      vn[u] = Lim<T>::hi();
+      if (i >= 0) {
+        if (hx) vx[u] = M[(r0 + i) * ld_t + cc];
+        if (hn) vn[u] = N[(r0 + i) * ld_t + cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 - u;
+      if (i >= 0) {
+        sx = vmax(sx, vx[u]);
+        sn = vmin(sn, vn[u]);
+        cr_set(Sx, (int)i, cr_bits(sx));
+        cr_set(Sn, (int)i, cr_bits(sn));
+      }
+    }
+  }
+  if (act) {
+    if (hx) omax[r0 * ld_out + c] = sx;  // window r0 is exactly the block
+    if (hn) omin[r0 * ld_out + c] = sn;
+  }
+  // next block, top-down: prefix max/min over rows r0+w .. r0+w-1+i
+  T px = Lim<T>::lo(), pn = Lim<T>::hi();
+  for (int64_t i0 = 1; i0 < nb; i0 += kColBatch) {
+    T vx[kColBatch], vn[kColBatch];
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 + u;
+      vx[u] = Lim<T>::lo();
+      vn[u] = Lim<T>::hi();
+      if (i < nb) {
+        if (hx) vx[u] = M[(r0 + w - 1 + i) * ld_t + cc];
+        if (hn) vn[u] = N[(r0 + w - 1 + i) * ld_t + cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) {
+      const int64_t i = i0 + u;
+      if (i < nb) {
+        px = vmax(px, vx[u]);
+        pn = vmin(pn, vn[u]);
+        if (act) {
+          if (hx) omax[(r0 + i) * ld_out + c] = vmax(cr_val<T>(cr_get(Sx, (int)i)), px);
+          if (hn) omin[(r0 + i) * ld_out + c] = vmin(cr_val<T>(cr_get(Sn, (int)i)), pn);
+        }
+      }
+    }
+  }
+}
+
 int64_t cols_max_window(int dtype) {
   const int64_t s = dtype == 1 ? 8 : (dtype == 3 ? 2 : 4);
   return (64 * 1024) / (2 * 64 * s);  // LDS: 2 images x 64 columns x w rows <= 64 KiB
@@ -158,6 +259,16 @@ hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld
   const dim3 grid((unsigned)((oc + 63) / 64), (unsigned)((orows + wr - 1) / wr));
   auto go = [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
+    if constexpr (sizeof(T) <= 4) {
+      // from w_rows 49 on (MI355X, 8192^2 float32 rows-then-columns: w = 63
+      // 0.55 against 0.64 ms; w = 48 equal, w <= 40 the LDS version ahead
+      // by 5-10%); MAXMIN_COLS_LDS=1 keeps the LDS version (experiments)
+      if (wr > 48 && wr <= 64 && !getenv("MAXMIN_COLS_LDS")) {
+        hipLaunchKernelGGL((k_cols_reg<T>), grid, dim3(64), 0, st, (const T*)tmax, (const T*)tmin, ld_t, rows, oc,
+                           wr, (T*)d_max, (T*)d_min, ld_out);
+        return hipGetLastError();
+      }
+    }
     if (gscratch)
       hipLaunchKernelGGL((k_cols<T, true>), grid, dim3(64), 0, st, (const T*)tmax, (const T*)tmin, ld_t, rows, oc,
                          wr, (T*)d_max, (T*)d_min, ld_out, (T*)gscratch);
