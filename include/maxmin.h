@@ -50,7 +50,7 @@ typedef enum {
   MAXMIN_ENOMEM = -2,      /* the library could not allocate its scratch memory */
   MAXMIN_EDEVICE = -3,     /* a HIP call failed */
   MAXMIN_EBUSY = -4,       /* scratch memory would have to grow while the stream is being captured */
-  MAXMIN_EUNSUPPORTED = -5 /* dtype or size outside what this build supports */
+  MAXMIN_EUNSUPPORTED = -5 /* dtype or size outside what the library supports */
 } maxmin_status_t;
 
 /* Strategies a call may use; all produce identical bits. */
