@@ -862,6 +862,200 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
   __syncthreads();
 }
 
+// ================================================== long windows, two passes
+// For a single series with K = ceil(w / 4096) > 1 chunks per block of w.
+// Pass 1 (k_chunk_agg): every chunk's max and min.  Pass 2 (k_chunk_col):
+// workgroup g walks column k = g mod K over a contiguous range of blocks;
+// the chunk w back that each chunk's windows start in is the same column's
+// previous chunk, which the workgroup loaded one step before and still
+// holds in registers, and the aggregates of the chunks between come from
+// pass 1.  Each input is read twice in all (once per pass) and nothing
+// waits on another workgroup; the look-back kernel reads the chunk w back
+// again from memory and waits on the records of the K-1 chunks before it.
+
+// The raw inputs of chunk slots [r0, r0 + V) (slots >= len read as 0).
+template <class T>
+__device__ __forceinline__ void col_load(const Series<T>& s, int64_t p0, int len, T (&v)[kChunkV]) {
+  constexpr int V = kChunkV, EV = 16 / (int)sizeof(T);
+  const int r0 = threadIdx.x * V;
+  const T* pa = nullptr;
+  if (p0 + len <= s.na) pa = s.a;
+  else if (p0 >= s.na) pa = s.b - s.na;
+  if (pa != nullptr && r0 + V <= len && (((uintptr_t)(pa + p0 + r0)) & 15) == 0) {
+#pragma unroll
+    for (int k = 0; k < V / EV; ++k) {
+      const u32x4 u = gload((const u32x4*)(pa + p0 + r0 + k * EV));
+      __builtin_memcpy(&v[k * EV], &u, 16);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = r0 + i < len ? src_at(s, p0 + r0 + i) : T(0);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_agg(Series<T> s, T* aggx, T* aggn) {
+  constexpr int V = kChunkV;
+  __shared__ T red[2][kChunkThreads / 64];
+  const int64_t w = s.w, n = s.n;
+  const int64_t K = (w + kChunkMax - 1) / kChunkMax, C = (w + K - 1) / K;
+  const int64_t nch = chunk_count(n, w);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t t = blockIdx.x; t < nch; t += gridDim.x) {
+    const int64_t b = t / K, k = t - b * K;
+    const int64_t p0 = b * w + k * C;
+    const int len = (int)min(min(C, w - k * C), n - p0);
+    T v[V];
+    col_load<T>(s, p0, len, v);
+    T mx = Lim<T>::lo(), mn = Lim<T>::hi();
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if ((int)threadIdx.x * V + i < len) {
+        mx = hmax(mx, v[i]);
+        mn = hmin(mn, v[i]);
+      }
+    for (int d = 32; d >= 1; d >>= 1) {
+      mx = hmax(mx, (T)__shfl_xor(mx, d, 64));
+      mn = hmin(mn, (T)__shfl_xor(mn, d, 64));
+    }
+    if (lane == 0) {
+      red[0][wave] = mx;
+      red[1][wave] = mn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T ax = red[0][0], an = red[1][0];
+      for (int q = 1; q < kChunkThreads / 64; ++q) {
+        ax = hmax(ax, red[0][q]);
+        an = hmin(an, red[1][q]);
+      }
+      aggx[t] = ax;
+      aggn[t] = an;
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_col(Series<T> s, const T* aggx, const T* aggn) {
+  constexpr int V = kChunkV;
+  __shared__ ChunkLds<T> sm;
+  __shared__ T edge[kChunkThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t w = s.w, n = s.n;
+  const int64_t K = (w + kChunkMax - 1) / kChunkMax, C = (w + K - 1) / K;
+  const int64_t NB = (n + w - 1) / w;  // blocks, the last one partial
+  const int64_t k = blockIdx.x % K, R = gridDim.x / K, rr = blockIdx.x / K;
+  const int64_t per = (NB + R - 1) / R;
+  const int64_t b0 = rr * per, b1 = min(NB, b0 + per);
+  const int lenfull = (int)min(C, w - k * C);
+  const int r0 = tid * V;
+  T prev[V], cur[V];  // raw inputs of the column's previous chunk and of this one
+  if (b0 >= b1 || b0 * w + k * C >= n) return;
+  if (b0 >= 1) col_load<T>(s, (b0 - 1) * w + k * C, lenfull, prev);  // whole: it ends before block b0
+  col_load<T>(s, b0 * w + k * C, (int)min((int64_t)lenfull, n - (b0 * w + k * C)), cur);
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t p0 = b * w + k * C;
+    if (p0 >= n) break;
+    const int len = (int)min((int64_t)lenfull, n - p0);
+    // the next chunk's loads fly while this one is computed
+    T nxt[V];
+    const int64_t p1 = p0 + w;
+    if (b + 1 < b1 && p1 < n) col_load<T>(s, p1, (int)min((int64_t)lenfull, n - p1), nxt);
+    // the aggregates this chunk needs, loaded now so their latency hides
+    // behind the scans: (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
+    const bool has_out = (p0 + len - 1) >= (w - 1);
+    T gx0 = Lim<T>::lo(), gn0 = Lim<T>::hi(), gx1 = Lim<T>::lo(), gn1 = Lim<T>::hi();
+    if (has_out && tid < 64) {
+      for (int64_t j = tid; j < K; j += 64) {
+        if (j < k) {
+          gx0 = hmax(gx0, aggx[b * K + j]);
+          gn0 = hmin(gn0, aggn[b * K + j]);
+        } else if (j > k && b >= 1) {
+          gx1 = hmax(gx1, aggx[(b - 1) * K + j]);
+          gn1 = hmin(gn1, aggn[(b - 1) * K + j]);
+        }
+      }
+    }
+    if (s.carry != nullptr) {
+      const int64_t cs = n - min(n, w - 1);
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (r0 + i < len && p0 + r0 + i >= cs) gstore(s.carry + (p0 + r0 + i - cs), cur[i]);
+    }
+    // behind slot r: the previous chunk's slot r + 1 (the start of the
+    // window that ends at slot r), from this lane, the next lane, or the
+    // next wavefront's lane 0
+    if (lane == 0) edge[wave] = prev[0];
+    __syncthreads();
+    T nb = __shfl_down(prev[0], 1, 64);
+    if (lane == 63) nb = wave + 1 < kChunkThreads / 64 ? edge[wave + 1] : T(0);
+    T ax[V], an[V], bx[V], bn[V];
+    const bool behind = b >= 1;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const bool vo = r0 + i < len;
+      ax[i] = vo ? cur[i] : Lim<T>::lo();
+      an[i] = vo ? cur[i] : Lim<T>::hi();
+      const bool vb = behind && r0 + i + 1 < lenfull;
+      const T h = i + 1 < V ? prev[i + 1 < V ? i + 1 : 0] : nb;
+      bx[i] = vb ? h : Lim<T>::lo();
+      bn[i] = vb ? h : Lim<T>::hi();
+    }
+#pragma unroll
+    for (int i = 1; i < V; ++i) {
+      ax[i] = hmax(ax[i - 1], ax[i]);
+      an[i] = hmin(an[i - 1], an[i]);
+    }
+#pragma unroll
+    for (int i = V - 2; i >= 0; --i) {
+      bx[i] = hmax(bx[i + 1], bx[i]);
+      bn[i] = hmin(bn[i + 1], bn[i]);
+    }
+    T epx = ax[V - 1], epn = an[V - 1], esx = bx[0], esn = bn[0], tx, tn;
+    wg_scan2<T>(epx, epn, esx, esn, tx, tn, sm);
+    if (has_out && tid < 64) {
+      T prx = gx0, prn = gn0, sux = gx1, sun = gn1;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        prx = hmax(prx, (T)__shfl_xor(prx, d, 64));
+        prn = hmin(prn, (T)__shfl_xor(prn, d, 64));
+        sux = hmax(sux, (T)__shfl_xor(sux, d, 64));
+        sun = hmin(sun, (T)__shfl_xor(sun, d, 64));
+      }
+      if (tid == 0) {
+        sm.dep[0] = prx;
+        sm.dep[1] = prn;
+        sm.dep[2] = sux;
+        sm.dep[3] = sun;
+      }
+    }
+    __syncthreads();
+    if (has_out) {
+      const T prx = hmax(sm.dep[0], epx), prn = hmin(sm.dep[1], epn);
+      const T sux = hmax(sm.dep[2], esx), sun = hmin(sm.dep[3], esn);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const int r = r0 + i;
+        if (r < len) {
+          sm.xs[lds_idx<T>(r)] = hmax(hmax(bx[i], sux), hmax(prx, ax[i]));
+          sm.hs[lds_idx<T>(r)] = hmin(hmin(bn[i], sun), hmin(prn, an[i]));
+        }
+      }
+      __syncthreads();
+      const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
+      if (s.omax) chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+      if (s.omin) chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      prev[i] = cur[i];
+      cur[i] = nxt[i];
+    }
+  }
+}
+
 template <int MODE, class T>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   __shared__ ChunkLds<T> sm;
@@ -1549,6 +1743,31 @@ int grid_cap(int dtype, int strategy) {
     });
   }
   return c;
+}
+
+hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st) {
+  const int64_t K = (a.w + kChunkMax - 1) / kChunkMax;
+  const int64_t nch = chunk_count(a.n, a.w);
+  if (nch <= 0) return hipSuccess;
+  if (K < 2 || a.mode != kJobOne) return hipErrorInvalidValue;
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    const Series<T> s = make_series<T>(a);
+    T* ax = (T*)agg;
+    T* an = ax + nch;
+    const int g1 = (int)std::min<int64_t>(nch, (int64_t)cu_count() * 8);
+    hipLaunchKernelGGL(k_chunk_agg<T>, dim3(g1), dim3(kChunkThreads), 0, st, s, ax, an);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // whole columns per workgroup group: a multiple of K workgroups (no
+    // workgroup waits on another, so the grid may exceed residency)
+    const int64_t cap = occupancy_grid(k_chunk_col<T>, kChunkThreads);
+    const int64_t g2 = std::max<int64_t>(1, cap / K) * K;
+    if (g2 > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chunk_col<T>, dim3((unsigned)g2), dim3(kChunkThreads), 0, st, s, (const T*)ax,
+                       (const T*)an);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st) {

@@ -118,6 +118,10 @@ enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3, kStratArg 
 int grid_cap(int dtype, int strategy);
 
 hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st);
+// Single series (a.mode 0) with more than one chunk per block of w: chunk
+// aggregates into agg (2 * chunk_count(n, w) elements), then one column of
+// chunks per workgroup (no look-back, no re-read of the chunk w back).
+hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st);
 
 // Batched setup: fills S descriptors (bytes: S * series_bytes()) and the
 // per-strategy tile prefix sums pre_tile / pre_chunk (S + 1 entries each);

@@ -118,13 +118,26 @@ def test_misaligned_outputs():
                 assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "min offsets %d/%d/%d" % (oi, ox, on))
 
 
+@pytest.mark.parametrize("lookback", ["0", "1"], ids=["columns", "lookback"])
 @pytest.mark.parametrize("strategy", [mm.STRATEGY_AUTO, mm.STRATEGY_CHUNK, mm.STRATEGY_RUN], ids=["auto", "chunk", "run"])
-def test_large_windows(strategy):
+def test_large_windows(strategy, lookback, monkeypatch):
+    """Windows of more than one chunk: the two-pass column kernels and
+    (MAXMIN_LONG_LOOKBACK=1) the look-back chunk kernel; every dtype, block
+    counts from one to dozens with a ragged last block, and a window
+    longer than 256 chunks."""
+    monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", lookback)
     rng = synth.rng_for("tests", 104)
     a = gen(300000, np.float32, rng, "walk")
     for w in (2048, 4096, 4100, 65536, 100000, 299999, 300000):
-        note("large-w n=300000 w=%d strategy=%d" % (w, strategy))
+        note("large-w n=300000 w=%d strategy=%d lookback=%s" % (w, strategy, lookback))
         check(a, w, "w=%d" % w, strategy=strategy)
+    if strategy == mm.STRATEGY_AUTO:
+        for dt in DTS:
+            for w, n in ((4097, 4097), (4097, 3 * 4097 + 5), (8192, 8192 * 7 + 4095), (12289, 12289 * 5 + 1),
+                         (20000, 20000 * 30 + 19999), (1 << 20, (1 << 20) + 77)):
+                b = gen(n, dt, rng, "walk" if w % 2 else "ties")
+                note("large-w dt=%s n=%d w=%d lookback=%s" % (np.dtype(dt).name, n, w, lookback))
+                check(b, w, "dt=%s n=%d w=%d" % (np.dtype(dt).name, n, w))
 
 
 @pytest.mark.parametrize("ranges", ["0", "8", "16", "32"])
@@ -135,6 +148,7 @@ def test_chunk_ticket_ranges(ranges, monkeypatch):
     with chunk counts that do not divide evenly into the ranges."""
     monkeypatch.setenv("MAXMIN_CHUNK_RANGES", ranges)
     monkeypatch.setenv("MAXMIN_CHUNK_RANGES_LONG", ranges)
+    monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", "1")  # ranges belong to the look-back kernel
     rng = synth.rng_for("tests", 106)
     for dt in (np.float32, np.float64):
         for w, n in ((1025, 1100003), (1500, 1500 * 700 + 311), (4096, 4096 * 1031 + 4095),
