@@ -56,7 +56,7 @@ typedef enum {
 /* Strategies a call may use; all produce identical bits. */
 typedef enum {
   MAXMIN_STRATEGY_AUTO = 0,  /* planner / autotuner decides */
-  MAXMIN_STRATEGY_TILE = 1,  /* LDS tile: power-of-two block prefix/suffix plus one middle block (w <= 4096; series of a batched call: w <= 2048) */
+  MAXMIN_STRATEGY_TILE = 1,  /* LDS tile: power-of-two block prefix/suffix plus whole blocks between (w <= 8192; series of a batched call: w <= 2048) */
   MAXMIN_STRATEGY_CHUNK = 2, /* window-aligned chunks, cross-workgroup look-back over chunk aggregates (any w) */
   MAXMIN_STRATEGY_RUN = 3    /* window-aligned chunks walked in runs, aggregates kept per workgroup (any w) */
 } maxmin_strategy_t;
@@ -203,7 +203,7 @@ int maxmin_autotune(int dtype, int64_t n, void* stream);
 /*
  * maxmin_tuning -- the current table for `dtype`: out6 = {tile run
  * (sub-tiles), batched run (sub-tiles), ranges for one-chunk windows, ranges
- * for longer windows, strategy for w > 4096 (MAXMIN_STRATEGY_CHUNK or _RUN),
+ * for longer windows, strategy for w > 8192 (MAXMIN_STRATEGY_CHUNK or _RUN),
  * 1 if measured by maxmin_autotune else 0}.  Host only.
  */
 int maxmin_tuning(int dtype, int64_t* out6);

@@ -68,7 +68,7 @@ struct Tuning {
   int batched_run = 16;  // sub-tiles per run, batched and 2-D row launches
   int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096; chunk strategy forced)
   int ranges_long = 0;   // chunk ticket ranges, longer windows
-  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 4096: chunk or run
+  int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 8192: chunk or run
   int tuned = 0;
 };
 std::mutex g_tune_mu;
@@ -97,7 +97,7 @@ int64_t run_chunks_per_run(int dt, int64_t n, int64_t w) {
   const int64_t cap = mm::grid_cap(dt, mm::kStratRun);
   return std::max<int64_t>(1, (nch + cap - 1) / cap);
 }
-// Planner: streaming tiles for w <= 4096, chunks with cross-workgroup
+// Planner: streaming tiles for w <= 8192, chunks with cross-workgroup
 // look-back above.  Chunk runs are used only when forced: on MI355X with
 // n = 2^28 float32 they ran slower than look-back chunks at w = 4096 and 8192
 // (1.46 ms against 0.83 and 0.88 ms).
@@ -108,7 +108,7 @@ int plan_strategy(int dt, int64_t n, int64_t w) {
   const bool run_ok = (w + mm::kCrMax - 1) / mm::kCrMax <= mm::kCrRing;
   if (f == MAXMIN_STRATEGY_CHUNK) return MAXMIN_STRATEGY_CHUNK;
   if (f == MAXMIN_STRATEGY_RUN && run_ok) return MAXMIN_STRATEGY_RUN;
-  if (w <= mm::kTileMaxW2) return MAXMIN_STRATEGY_TILE;
+  if (w <= mm::kTileMaxW4) return MAXMIN_STRATEGY_TILE;
   if (!f && run_ok && tuning(dt).long_strategy == MAXMIN_STRATEGY_RUN) return MAXMIN_STRATEGY_RUN;
   return MAXMIN_STRATEGY_CHUNK;
 }
@@ -152,7 +152,12 @@ bool long_lookback(int64_t w) {
 }
 
 // Which tile kernel a single series or a row pass of window w runs.
-int tile_kind(int64_t w) { return w <= mm::kTileMaxW ? mm::kStratTile : mm::kStratTile2; }
+int tile_kind(int64_t w) {
+  return w <= mm::kTileMaxW    ? mm::kStratTile
+         : w <= mm::kTileMaxW2 ? mm::kStratTile2
+         : w <= 3 * mm::kTileOut ? mm::kStratTile3
+                                 : mm::kStratTile4;
+}
 
 // ------------------------------------------------------------ workspaces
 typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*, int64_t> GraphKey;
@@ -318,9 +323,9 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     const int ks = tile_kind(a.w);
     const int cap = mm::grid_cap(dt, ks);
     // a run re-reads the w-1 inputs after it: runs 4x longer for windows
-    // over two sub-tiles (MI355X, n = 2^28 float32, w = 2049..4096: 64
-    // sub-tiles 0.71-0.73 ms, 32: 0.72-0.73, 16: 0.74-0.75)
-    const int64_t rmax = (int64_t)tuning(dt).tile_run * (ks == mm::kStratTile2 ? 4 : 1) * mm::kTileOut;
+    // over more than one sub-tile (MI355X, n = 2^28 float32, w =
+    // 2049..4096: 64 sub-tiles 0.71-0.73 ms, 32: 0.72-0.73, 16: 0.74-0.75)
+    const int64_t rmax = (int64_t)tuning(dt).tile_run * (ks == mm::kStratTile ? 1 : 4) * mm::kTileOut;
     a.run = mm::run_length(a.n - a.w + 1, cap, rmax);
     if (const char* e = getenv("MAXMIN_TILE_RUN")) {
       const int64_t r = atoll(e) / mm::kTileOut * mm::kTileOut;

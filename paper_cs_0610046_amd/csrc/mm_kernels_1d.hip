@@ -140,6 +140,7 @@ template <class T> struct TileLds {
   T pm[lds_len<T>(2 * kTileOut)];  // PRE (max) ring, indexed by position mod 2*kTileOut
   T pn[lds_len<T>(2 * kTileOut)];  // PRE (min) ring
   T wt[4][kTileThreads / 64];      // wavefront totals (blocks of two or four wavefronts)
+  T st[2][8];                      // LAG >= 3: sub-tile totals, indexed by sub-tile mod 8
 };
 
 // Series and outputs need not be 16-byte aligned (a packed batch puts
@@ -289,9 +290,12 @@ __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_
 // location, the position in the series).
 // LAG: sub-tiles between a window's first and last element.  LAG 1 (w <=
 // 2048): blocks up to 1024, the windows starting in P_{k-1} are emitted
-// once P_k is scanned.  LAG 2 (2048 < w <= 4096): blocks of one whole
-// sub-tile (four wavefronts), the windows starting in P_{k-2} are emitted
-// once P_k is scanned, so two sub-tiles of SUF stay in registers.
+// once P_k is scanned.  LAG L >= 2 ((L-1) 2048 < w <= L 2048): blocks of
+// one whole sub-tile (four wavefronts), the windows starting in P_{k-L} are
+// emitted once P_k is scanned, so L sub-tiles of SUF stay in registers;
+// their ends lie in P_{k-1} or P_k (PRE from the ring) and the whole
+// sub-tiles between are one block (L = 2: PRE at its end, from the ring)
+// or several (L >= 3: the totals of the last 8 sub-tiles, kept in LDS).
 template <class T, bool ARG, int LAG>
 __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t R1,
                                          TileLds<typename ElemOf<T, ARG>::type>& sm, int64_t* amax,
@@ -301,7 +305,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   constexpr int NT = kTileThreads, V = kTileV, TT = kTileOut, RING = 2 * kTileOut;
   const int tid = threadIdx.x;
   const int w = (int)s.w;
-  static_assert(LAG == 1 || LAG == 2, "emission lag of one or two sub-tiles");
+  static_assert(LAG >= 1 && LAG <= 4, "emission lag of one to four sub-tiles");
   const int lgB = 31 - __builtin_clz((unsigned)min(w, LAG == 1 ? kTileMaxBlock : TT));
   const int B = 1 << lgB;
   const int m = B > V ? B / V : 1;  // lanes per block (128, 256: two, four wavefronts)
@@ -324,8 +328,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   const bool last_run = R1 == nout;
 
   T cur[V], nxt[V];
-  E sx[V], sn[V];  // SUF of the previous sub-tile's positions
-  E tx[V], tn[V];  // LAG 2: SUF of the sub-tile before that
+  E hx[LAG][V], hn[LAG][V];  // SUF of P_{k-1} (index 0) .. P_{k-LAG}
   run_load<T>(s, vbase, din, R0 + tid * V, lim, cur);
   for (int k = 0; k < nsub; ++k) {
     const int pr0 = k * TT + tid * V;  // position of cur[0], relative to R0
@@ -464,6 +467,12 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
         sm.pm[lds_idx<E>(slot + i)] = px[i];
         sm.pn[lds_idx<E>(slot + i)] = pn[i];
       }
+      if constexpr (LAG >= 3) {
+        if (tid == NT - 1) {  // PRE at the sub-tile's last position: its total
+          sm.st[0][k & 7] = px[V - 1];
+          sm.st[1][k & 7] = pn[V - 1];
+        }
+      }
       __syncthreads();  // PRE of P_k visible
     }
     if (k >= LAG) {
@@ -471,15 +480,29 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       // end and the whole block strictly inside, if any (both from the ring;
       // the ends lie in P_{k-1} or P_k)
       const int qr0 = pr0 - LAG * TT;
+      // LAG >= 3: totals of the whole sub-tiles between P_{k-LAG} and the
+      // window's last sub-tile, P_{k-1} (mx1) or P_k (mx0)
+      E mx1 = elem(Lim<T>::lo(), 0, et), mn1 = elem(Lim<T>::hi(), 0, et), mx0 = mx1, mn0 = mn1;
+      if constexpr (LAG >= 3) {
+        for (int j = k - LAG + 1; j <= k - 2; ++j) {
+          mx1 = hmax(mx1, sm.st[0][j & 7]);
+          mn1 = hmin(mn1, sm.st[1][j & 7]);
+        }
+        mx0 = hmax(mx1, sm.st[0][(k - 1) & 7]);
+        mn0 = hmin(mn1, sm.st[1][(k - 1) & 7]);
+      }
       E ox[V], on[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const int q = qr0 + i, e = q + w - 1;
-        const E fx = LAG == 2 ? tx[i] : sx[i], fn = LAG == 2 ? tn[i] : sn[i];
-        E rx = hmax(fx, sm.pm[lds_idx<E>(e & (RING - 1))]);
-        E rn = hmin(fn, sm.pn[lds_idx<E>(e & (RING - 1))]);
+        E rx = hmax(hx[LAG - 1][i], sm.pm[lds_idx<E>(e & (RING - 1))]);
+        E rn = hmin(hn[LAG - 1][i], sm.pn[lds_idx<E>(e & (RING - 1))]);
         const int b1 = q >> lgB, b2 = e >> lgB;
-        if (b2 >= b1 + 2) {
+        if constexpr (LAG >= 3) {
+          const bool last = b2 == b1 + LAG;  // ends in P_k
+          rx = hmax(rx, last ? mx0 : mx1);
+          rn = hmin(rn, last ? mn0 : mn1);
+        } else if (b2 >= b1 + 2) {
           const int mi = (((b1 + 2) << lgB) - 1) & (RING - 1);
           rx = hmax(rx, sm.pm[lds_idx<E>(mi)]);
           rn = hmin(rn, sm.pn[lds_idx<E>(mi)]);
@@ -507,13 +530,14 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      if constexpr (LAG == 2) {
-        tx[i] = sx[i];
-        tn[i] = sn[i];
+#pragma unroll
+      for (int g = LAG - 1; g >= 1; --g) {
+        hx[g][i] = hx[g - 1][i];
+        hn[g][i] = hn[g - 1][i];
       }
       if (live) {
-        sx[i] = ux[i];
-        sn[i] = un[i];
+        hx[0][i] = ux[i];
+        hn[0][i] = un[i];
       }
       cur[i] = nxt[i];
     }
@@ -1727,8 +1751,8 @@ template <class K> static int occupancy_grid(K kernel, int threads) {
 }
 
 int grid_cap(int dtype, int strategy) {
-  static int cap[6][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratArg2) return 0;
+  static int cap[8][4] = {};
+  if (dtype < 0 || dtype > 3 || strategy < kStratTile || strategy > kStratTile4) return 0;
   int& c = cap[strategy - 1][dtype];
   if (!c) {
     (void)dispatch(dtype, [&](auto* p) {
@@ -1738,6 +1762,8 @@ int grid_cap(int dtype, int strategy) {
           : strategy == kStratArg   ? occupancy_grid(k_tile<kJobOne, T, true>, kTileThreads)
           : strategy == kStratTile2 ? occupancy_grid(k_tile<kJobOne, T, false, 2>, kTileThreads)
           : strategy == kStratArg2  ? occupancy_grid(k_tile<kJobOne, T, true, 2>, kTileThreads)
+          : strategy == kStratTile3 ? occupancy_grid(k_tile<kJobOne, T, false, 3>, kTileThreads)
+          : strategy == kStratTile4 ? occupancy_grid(k_tile<kJobOne, T, false, 4>, kTileThreads)
                                     : occupancy_grid(k_crun<kJobDescs, T>, kChunkThreads);
       return hipSuccess;
     });
@@ -1783,6 +1809,19 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
       } else {
         if (a.w <= kTileMaxW || a.w > kTileMaxW2) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_tile<kJobOne, T, true, 2>), g, dim3(kTileThreads), 0, st, j);
+      }
+    } else if (strategy == kStratTile3 || strategy == kStratTile4) {
+      // windows ending three or four sub-tiles after they start
+      const int L = strategy == kStratTile3 ? 3 : 4;
+      if (a.w <= (L - 1) * (int64_t)kTileOut || a.w > L * (int64_t)kTileOut) return hipErrorInvalidValue;
+      if (a.mode == kJobOne) {
+        if (L == 3) hipLaunchKernelGGL((k_tile<kJobOne, T, false, 3>), g, dim3(kTileThreads), 0, st, j);
+        else hipLaunchKernelGGL((k_tile<kJobOne, T, false, 4>), g, dim3(kTileThreads), 0, st, j);
+      } else if (a.mode == kJobRows) {
+        if (L == 3) hipLaunchKernelGGL((k_tile<kJobRows, T, false, 3>), g, dim3(kTileThreads), 0, st, j);
+        else hipLaunchKernelGGL((k_tile<kJobRows, T, false, 4>), g, dim3(kTileThreads), 0, st, j);
+      } else {
+        return hipErrorInvalidValue;
       }
     } else if (strategy == kStratTile2) {
       // the two-sub-tile emission lag needs every window to end past its

@@ -18,6 +18,8 @@ constexpr int64_t kTileMaxW = 2 * kTileMaxBlock;            // 2048: w <= 2 * bl
 // Second instantiation (kStratTile2, single series and rows): blocks of a
 // whole sub-tile, windows end at most two sub-tiles after they start.
 constexpr int64_t kTileMaxW2 = 2 * kTileOut;                // 4096
+// ... and with windows ending three or four sub-tiles on (kStratTile3/4)
+constexpr int64_t kTileMaxW4 = 4 * kTileOut;                // 8192
 // Longest run: on MI355X (n = 2^28 and 2^30 float32) runs of 16 sub-tiles,
 // dealt round robin, beat one long run per workgroup by 5-6%.
 constexpr int64_t kTileRunMax = 16 * kTileOut;
@@ -111,8 +113,18 @@ struct JobArgs {
 
 // kStratArg: the tile kernel carrying locations (arg max/min filter).
 // kStratTile2 / kStratArg2: the same kernels for 2048 < w <= 4096 (single
-// series, rows).
-enum Strategy : int { kStratTile = 1, kStratChunk = 2, kStratRun = 3, kStratArg = 4, kStratTile2 = 5, kStratArg2 = 6 };
+// series, rows); kStratTile3 / kStratTile4: 4096 < w <= 6144 / 6144 < w <=
+// 8192.
+enum Strategy : int {
+  kStratTile = 1,
+  kStratChunk = 2,
+  kStratRun = 3,
+  kStratArg = 4,
+  kStratTile2 = 5,
+  kStratArg2 = 6,
+  kStratTile3 = 7,
+  kStratTile4 = 8
+};
 
 // Occupancy-derived persistent grid sizes (computed once per device).
 int grid_cap(int dtype, int strategy);

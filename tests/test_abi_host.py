@@ -131,11 +131,13 @@ def test_planner(lib):
     assert binding.maxmin_plan(np.float32, 1 << 20, 2048) == binding.STRATEGY_TILE
     assert binding.maxmin_plan(np.float32, 1 << 20, 2049) == binding.STRATEGY_TILE
     assert binding.maxmin_plan(np.float32, 1 << 20, 4096) == binding.STRATEGY_TILE
-    assert binding.maxmin_plan(np.float32, 1 << 20, 4097) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)
+    assert binding.maxmin_plan(np.float32, 1 << 20, 4097) == binding.STRATEGY_TILE
+    assert binding.maxmin_plan(np.float32, 1 << 20, 8192) == binding.STRATEGY_TILE
+    assert binding.maxmin_plan(np.float32, 1 << 20, 8193) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)
     binding.maxmin_set_strategy(binding.STRATEGY_CHUNK)
     assert binding.maxmin_plan(np.float32, 1 << 20, 64) == binding.STRATEGY_CHUNK
     binding.maxmin_set_strategy(binding.STRATEGY_TILE)
-    assert binding.maxmin_plan(np.float32, 1 << 20, 5000) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)  # tile cannot
+    assert binding.maxmin_plan(np.float32, 1 << 20, 9000) in (binding.STRATEGY_CHUNK, binding.STRATEGY_RUN)  # tile cannot
     binding.maxmin_set_strategy(binding.STRATEGY_AUTO)
 
 

@@ -67,8 +67,8 @@ def test_plain_all_windows(dt):
 def test_forced_strategies_agree(strategy):
     rng = synth.rng_for("tests", 101)
     for dt in DTS:
-        for w in [1, 2, 5, 33, 100, 512, 700, 1024, 1025, 1500, 2048, 2049, 3000, 4096] + \
-                 ([4097, 9000] if strategy != mm.STRATEGY_TILE else []):
+        for w in [1, 2, 5, 33, 100, 512, 700, 1024, 1025, 1500, 2048, 2049, 3000, 4096, 4097, 6144, 6145, 8192] + \
+                 ([8193, 9000] if strategy != mm.STRATEGY_TILE else []):
             n = int(rng.integers(w, 3 * 2048 + w))
             a = gen(n, dt, rng, "walk" if w % 2 else "ties")
             note("forced=%d dt=%s n=%d w=%d" % (strategy, np.dtype(dt).name, n, w))
@@ -160,10 +160,11 @@ def test_chunk_ticket_ranges(ranges, monkeypatch):
 
 @pytest.mark.parametrize("run", [None, "2048", "4096", "10000"])
 def test_tile_windows_over_two_subtiles(run, monkeypatch):
-    """2048 < w <= 4096: the tile kernel with blocks of a whole sub-tile,
-    whose windows end up to two sub-tiles after they start.  Runs of one,
-    two and four sub-tiles (so every run boundary re-reads a two-sub-tile
-    halo), n from a single window to several runs with a ragged tail,
+    """2048 < w <= 8192: the tile kernel with blocks of a whole sub-tile,
+    whose windows end two, three or four sub-tiles after they start (the
+    whole sub-tiles between from their totals).  Runs of one, two and four
+    sub-tiles (so every run boundary re-reads a halo of up to four
+    sub-tiles), n from a single window to several runs with a ragged tail,
     ties and ramps, misaligned input and outputs, max-only and min-only."""
     import torch
     if run is not None:
@@ -171,7 +172,7 @@ def test_tile_windows_over_two_subtiles(run, monkeypatch):
     rng = synth.rng_for("tests", 108)
     for dt in DTS:
         tdt = to_dev(np.zeros(1, dt)).dtype
-        for w in (2049, 2050, 2304, 3000, 4095, 4096):
+        for w in (2049, 2050, 2304, 3000, 4095, 4096, 4097, 5000, 6144, 6145, 7777, 8192):
             assert mm.maxmin_plan(dt, 1 << 20, w) == mm.STRATEGY_TILE
             for n in sorted({w, w + 1, w + 2047, w + 2048, w + 4095, 3 * 2048 + w + 5, 9 * 2048 + 13}):
                 kind = ["walk", "ties", "ramp"][(n + w) % 3]
@@ -179,27 +180,28 @@ def test_tile_windows_over_two_subtiles(run, monkeypatch):
                 note("tile2 run=%s dt=%s n=%d w=%d kind=%s" % (run, np.dtype(dt).name, n, w, kind))
                 check(a, w, "tile2 n=%d w=%d %s" % (n, w, kind))
         # misaligned input and outputs; one output only
-        w, n = 3001, 40000 + 3
-        a = gen(n, dt, rng, "walk")
-        omx, omn = oracle.wedge(a, w)
-        no = n - w + 1
-        for oi, ox, on in ((1, 3, 2), (2, 0, 0)):
-            buf = to_dev(np.concatenate([np.zeros(oi, dt), a]))
-            bmx = torch.empty(no + 8, dtype=tdt, device="cuda")
-            bmn = torch.empty(no + 8, dtype=tdt, device="cuda")
-            note("tile2 misaligned run=%s dt=%s in=%d max=%d min=%d" % (run, np.dtype(dt).name, oi, ox, on))
-            mm.maxmin_filter(buf[oi:], w, bmx[ox:ox + no], bmn[on:on + no])
+        for w in (3001, 5001, 7001):
+            n = 40000 + 3
+            a = gen(n, dt, rng, "walk")
+            omx, omn = oracle.wedge(a, w)
+            no = n - w + 1
+            for oi, ox, on in ((1, 3, 2), (2, 0, 0)):
+                buf = to_dev(np.concatenate([np.zeros(oi, dt), a]))
+                bmx = torch.empty(no + 8, dtype=tdt, device="cuda")
+                bmn = torch.empty(no + 8, dtype=tdt, device="cuda")
+                note("tile2 misaligned run=%s dt=%s in=%d max=%d min=%d" % (run, np.dtype(dt).name, oi, ox, on))
+                mm.maxmin_filter(buf[oi:], w, bmx[ox:ox + no], bmn[on:on + no])
+                torch.cuda.synchronize()
+                assert_bits_equal(to_host(bmx[ox:ox + no], dt), omx, "tile2 max offsets %d/%d/%d" % (oi, ox, on))
+                assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "tile2 min offsets %d/%d/%d" % (oi, ox, on))
+            x = to_dev(a)
+            note("tile2 one output run=%s dt=%s" % (run, np.dtype(dt).name))
+            gmx, none = mm.maxmin_filter(x, w, which="max")
+            none2, gmn = mm.maxmin_filter(x, w, which="min")
+            assert none is None and none2 is None
             torch.cuda.synchronize()
-            assert_bits_equal(to_host(bmx[ox:ox + no], dt), omx, "tile2 max offsets %d/%d/%d" % (oi, ox, on))
-            assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "tile2 min offsets %d/%d/%d" % (oi, ox, on))
-        x = to_dev(a)
-        note("tile2 one output run=%s dt=%s" % (run, np.dtype(dt).name))
-        gmx, none = mm.maxmin_filter(x, w, which="max")
-        none2, gmn = mm.maxmin_filter(x, w, which="min")
-        assert none is None and none2 is None
-        torch.cuda.synchronize()
-        assert_bits_equal(to_host(gmx, dt), omx, "tile2 max-only")
-        assert_bits_equal(to_host(gmn, dt), omn, "tile2 min-only")
+            assert_bits_equal(to_host(gmx, dt), omx, "tile2 max-only")
+            assert_bits_equal(to_host(gmn, dt), omn, "tile2 min-only")
 
 
 def test_repeatable_bits():

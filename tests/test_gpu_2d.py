@@ -32,7 +32,7 @@ def test_2d_small_images(dt, path2d):
     cases = [(1, 1, 1, 1), (5, 7, 2, 3), (64, 64, 3, 3), (100, 300, 15, 15), (257, 2100, 63, 63),
              (130, 3000, 7, 1500), (70, 50, 70, 1), (33, 4100, 1, 1025), (300, 40, 128 if dt != np.float64 else 64, 5),
              (700, 90, 200, 4), (20, 9000, 3, 3000), (9, 4200, 2, 4096), (6, 2049, 4, 2049), (150, 500, 40, 9),
-             (200, 333, 49, 2)]
+             (200, 333, 49, 2), (7, 9000, 2, 6000), (5, 8200, 3, 8192)]
     for rows, cols, wr, wc in cases:
         if dt == np.uint16:
             a = synth.uniform_u16((rows, cols), rng)
