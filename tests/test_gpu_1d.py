@@ -218,8 +218,10 @@ def test_repeatable_bits():
             assert torch.equal(r[0], r0[0]) and torch.equal(r[1], r0[1])
 
 
-@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000])
-def test_stream_chunks_equal_one_shot(w):
+@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000, 7000, 9000, 20000])
+def test_stream_chunks_equal_one_shot(w, monkeypatch):
+    if w == 20000:  # the look-back chunk kernel for a push too (w = 9000 takes the column kernels)
+        monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", "1")
     import torch
     rng = synth.rng_for("tests", 106)
     for dt in (np.float32, np.float64, np.int32):
