@@ -191,18 +191,19 @@ int maxmin_envelope_batched(int dtype, const void* d_in, const int64_t* d_in_off
  * the current device and keep the fastest, process-wide: the tile run length
  * (sub-tiles per run), the ticket-range count of one-chunk windows, the
  * strategy (chunk or chunk runs) and range count of longer windows, and the
- * run length of batched launches.  Allocates and frees 3 n elements of
- * device memory (n = 0: 2^26) and synchronises `stream`; results of every
- * call stay bit-identical whatever it picks.  Not during graph capture
- * (EBUSY).  Calls made concurrently on other threads may see the table
- * change midway (each launch reads it once).
+ * run length of the 2-D filter's row pass.  Allocates and frees 3 n elements
+ * of device memory (n = 0: 2^26), leaves the stream's 2-D scratch images
+ * (up to 2 n elements) in place for later calls, and synchronises `stream`;
+ * results of every call stay bit-identical whatever it picks.  Not during
+ * graph capture (EBUSY).  Calls made concurrently on other threads may see
+ * the table change midway (each launch reads it once).
  * Errors: EINVAL for an unknown dtype or 0 < n < 2^20; ENOMEM.
  */
 int maxmin_autotune(int dtype, int64_t n, void* stream);
 
 /*
  * maxmin_tuning -- the current table for `dtype`: out6 = {tile run
- * (sub-tiles), batched run (sub-tiles), ranges for one-chunk windows, ranges
+ * (sub-tiles), 2-D row-pass run (sub-tiles), ranges for one-chunk windows, ranges
  * for longer windows, strategy for w > 8192 (MAXMIN_STRATEGY_CHUNK or _RUN),
  * 1 if measured by maxmin_autotune else 0}.  Host only.
  */

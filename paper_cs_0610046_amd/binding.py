@@ -313,7 +313,7 @@ def maxmin_tuning(dtype):
     """The planner's launch parameters for ``dtype`` (host only)."""
     out = (ctypes.c_int64 * 6)()
     _check(lib().maxmin_tuning(dtype_code(dtype), out))
-    return {"tile_run_subtiles": out[0], "batched_run_subtiles": out[1], "chunk_ranges_one_chunk": out[2],
+    return {"tile_run_subtiles": out[0], "rows_run_subtiles": out[1], "chunk_ranges_one_chunk": out[2],
             "chunk_ranges_long": out[3], "long_window_strategy": {2: "chunk", 3: "run"}.get(out[4], out[4]),
             "measured": bool(out[5])}
 

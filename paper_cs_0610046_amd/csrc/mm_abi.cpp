@@ -65,7 +65,7 @@ std::atomic<int> g_force{0};
 // device at hand.  Environment variables still override (experiments).
 struct Tuning {
   int tile_run = 16;     // sub-tiles per run, single-series tile launches
-  int batched_run = 16;  // sub-tiles per run, batched and 2-D row launches
+  int batched_run = 16;  // sub-tiles per run, row pass of the 2-D filter
   int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096; chunk strategy forced)
   int ranges_long = 0;   // chunk ticket ranges, longer windows
   int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 8192: chunk or run
@@ -592,7 +592,10 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
   if ((r = ensure_batch(ws, S))) return r;
   if ((r = ensure_ring(ws, int64_t(1) << kRingMaxLg))) return r;
 
-  const int64_t brun = (int64_t)tuning(dtype).batched_run * mm::kTileOut;
+  // tiles of one sub-tile: the tile kernel streams each workgroup's
+  // contiguous range of them series by series, so their size only sets
+  // how evenly the ranges split
+  const int64_t brun = mm::kRunBatched;
   auto enqueue = [&]() -> hipError_t {
     int64_t* pre_tile = ws->pre;
     int64_t* pre_chunk = ws->pre + (S + 1);
@@ -897,9 +900,7 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
   if (n < (int64_t(1) << 20)) return fail(MAXMIN_EINVAL, "maxmin_autotune: n=%lld < 2^20", (long long)n);
   hipStream_t st = (hipStream_t)stream;
   if (capturing(st)) return fail(MAXMIN_EBUSY, "maxmin_autotune: the stream is being captured");
-  const int S = 64;
   void *in = nullptr, *mx = nullptr, *mn = nullptr;
-  int64_t* arr = nullptr;  // in_offsets [S+1], windows [S], out_offsets [S+1]
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const Tuning before = tuning(dtype);
   int r = MAXMIN_OK;
@@ -909,22 +910,15 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
     if (in) hipFree(in);
     if (mx) hipFree(mx);
     if (mn) hipFree(mn);
-    if (arr) hipFree(arr);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
   };
   if (hipMalloc(&in, (size_t)n * s) != hipSuccess || hipMalloc(&mx, (size_t)n * s) != hipSuccess ||
-      hipMalloc(&mn, (size_t)n * s) != hipSuccess || hipMalloc((void**)&arr, (size_t)(3 * S + 2) * 8) != hipSuccess) {
+      hipMalloc(&mn, (size_t)n * s) != hipSuccess) {
     cleanup();
     return fail(MAXMIN_ENOMEM, "maxmin_autotune: cannot allocate %lld elements", (long long)n);
   }
-  std::vector<int64_t> h(3 * S + 2);
-  const int64_t len = n / S, wb = 256;
-  for (int k = 0; k <= S; ++k) h[k] = k * len;
-  for (int k = 0; k < S; ++k) h[S + 1 + k] = wb;
-  for (int k = 0; k <= S; ++k) h[2 * S + 1 + k] = k * (len - wb + 1);
   hipError_t e = hipMemsetAsync(in, 0x3c, (size_t)n * s, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(arr, h.data(), h.size() * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) {
@@ -983,9 +977,10 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
   if (!r && n >= 4 * 65536) pick(&Tuning::long_strategy, {MAXMIN_STRATEGY_CHUNK, MAXMIN_STRATEGY_RUN}, filt(65536));
   if (!r && n >= 4 * 65536 && best.long_strategy == MAXMIN_STRATEGY_CHUNK)
     pick(&Tuning::ranges_long, {0, 16}, filt(65536));
-  if (!r)
+  if (!r)  // the series as an image of 8192 columns, 63 x 63 windows (rows then columns)
     pick(&Tuning::batched_run, {8, 16, 32}, std::function<int()>([=]() {
-           return maxmin_filter_batched(dtype, in, arr, arr + S + 1, arr + 2 * S + 1, S, mx, mn, stream);
+           const int64_t cols = 8192, rows = n / cols;
+           return maxmin_filter_2d(dtype, in, rows, cols, cols, 63, 63, mx, mn, cols - 62, stream);
          }));
   const int rr = r;
   cleanup();

@@ -551,6 +551,31 @@ template <int MODE, class T, bool ARG = false, int LAG = 1>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
   __shared__ TileLds<typename ElemOf<T, ARG>::type> sm;
   const int64_t nruns = job_tiles<MODE>(job);
+  if constexpr (MODE == kJobDescs) {
+    // Described series: workgroup g takes the g-th of gridDim.x equal,
+    // contiguous ranges of the tiles (short ones: a sub-tile each) and
+    // streams each series' part of it as one run.  One search finds the
+    // range's first series; after that the walk only steps to the next
+    // series, and a series' tiles in the range are never split into runs.
+    const int64_t a = nruns * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t b = nruns * ((int64_t)blockIdx.x + 1) / gridDim.x;
+    if (a >= b) return;
+    int64_t k = find_series(job.pre, job.S, a);
+    int64_t t = a, base = job.pre[k];
+    while (t < b) {
+      const int64_t next = job.pre[k + 1];  // k < S: pre[S] = nruns > t
+      if (next > t) {
+        const Series<T> s = job.descs[k];
+        const int64_t nout = s.n - s.w + 1;
+        const int64_t hi = min(b, next);
+        run_body<T, ARG, LAG>(s, (t - base) * job.run, min(nout, (hi - base) * job.run), sm, job.amax, job.amin);
+        t = hi;
+      }
+      base = next;
+      ++k;
+    }
+    return;
+  }
   for (int64_t t = blockIdx.x; t < nruns; t += gridDim.x) {
     int64_t local, gbase;
     const Series<T> s = job_series<MODE>(job, t, local, gbase);

@@ -23,7 +23,9 @@ constexpr int64_t kTileMaxW4 = 4 * kTileOut;                // 8192
 // Longest run: on MI355X (n = 2^28 and 2^30 float32) runs of 16 sub-tiles,
 // dealt round robin, beat one long run per workgroup by 5-6%.
 constexpr int64_t kTileRunMax = 16 * kTileOut;
-constexpr int64_t kRunBatched = 16 * kTileOut;              // windows per run in batched / rows jobs
+// Tile of a described-series job (batched calls, serving batches): one
+// sub-tile of windows; each workgroup streams a contiguous range of tiles.
+constexpr int64_t kRunBatched = kTileOut;
 
 // Chunk strategy: window-aligned chunks of at most kChunkMax inputs.
 constexpr int kChunkThreads = 256;

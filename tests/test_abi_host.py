@@ -77,7 +77,7 @@ def test_argument_errors_without_gpu(lib):
 
 def test_tuning_table_and_autotune_arguments(lib):
     t = binding.maxmin_tuning(np.float32)
-    assert t == {"tile_run_subtiles": 16, "batched_run_subtiles": 16, "chunk_ranges_one_chunk": 16,
+    assert t == {"tile_run_subtiles": 16, "rows_run_subtiles": 16, "chunk_ranges_one_chunk": 16,
                  "chunk_ranges_long": 0, "long_window_strategy": "chunk", "measured": False}
     assert lib.maxmin_autotune(9, 0, None) == binding.MAXMIN_EINVAL
     assert lib.maxmin_autotune(0, 1000, None) == binding.MAXMIN_EINVAL  # below 2^20, checked before any device call

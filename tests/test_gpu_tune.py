@@ -18,7 +18,7 @@ def test_autotune_then_parity():
     note("autotune float32 n=2^22")
     t = mm.maxmin_autotune(np.float32, 1 << 22)
     assert t["measured"]
-    assert t["tile_run_subtiles"] in (8, 16, 32, 64) and t["batched_run_subtiles"] in (8, 16, 32)
+    assert t["tile_run_subtiles"] in (8, 16, 32, 64) and t["rows_run_subtiles"] in (8, 16, 32)
     assert t["chunk_ranges_one_chunk"] in (0, 8, 16, 32) and t["chunk_ranges_long"] in (0, 16)
     assert t["long_window_strategy"] in ("chunk", "run")
     rng = synth.rng_for("tests", 800)
