@@ -151,27 +151,96 @@ template <class T> struct TileLds {
 // the neighbouring lane with one shuffle each; the wavefront's edge lanes
 // load (store) those few elements singly.
 
-// v[i] = input p + i, from aligned vectors holding p - D .. p - D + 7
-template <class T, int D>
-__device__ __forceinline__ void load_shifted(const T* vb, int64_t p, T (&v)[kTileV]) {
-  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
-  T raw[V];
-#pragma unroll
-  for (int k = 0; k < V / EV; ++k) {
-    const u32x4 u = gload((const u32x4*)(vb + p - D + k * EV));
-    __builtin_memcpy(&raw[k * EV], &u, 16);
+// An empty statement that reads x: the compiler waits for x's load right
+// here (and knows it needs no later wait), instead of where x is next read.
+template <class T> __device__ __forceinline__ void settle(const T& x) {
+  if constexpr (sizeof(T) == 8) {
+    uint64_t u;
+    __builtin_memcpy(&u, &x, 8);
+    asm volatile("" ::"v"(u));
+  } else {
+    uint32_t u = 0;
+    __builtin_memcpy(&u, &x, sizeof(T));
+    asm volatile("" ::"v"(u));
   }
+}
+
+// Workgroup barrier ordering LDS only.  The tile kernel's wavefronts share
+// nothing through global memory; __syncthreads would also make each
+// wavefront wait for its outstanding global stores to complete.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Elements a lane may need beyond its aligned vectors (the largest shift).
+template <class T> constexpr int kTileEx = 16 / (int)sizeof(T) - 1;
+
+// Issue the loads of the 8 inputs at positions p .. p+7 and nothing else,
+// so the sub-tile's prefetch stays in flight while the current one is
+// computed.  Where the wavefront's positions lie in the segment vb below
+// lim, v gets the aligned 16-byte vectors holding p - d .. p - d + 7 (the
+// same instructions whatever the misalignment d, so no branch joins two
+// sets of loaded registers) and lane 63 the d inputs after them in ex; the
+// result is true when run_fix must still shift them by d.  Elsewhere
+// (a run's end, a series split over two buffers) v gets the inputs one by
+// one, those >= lim as 0 (never used).
+template <class T>
+__device__ __forceinline__ bool run_issue(const Series<T>& s, const T* vb, int d, int64_t p, int64_t lim,
+                                          T (&v)[kTileV], T (&ex)[kTileEx<T>]) {
+  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
+  const int64_t pw = p - (int64_t)(threadIdx.x & 63) * V;  // the wavefront's first position
+  // the same for every lane; readfirstlane lets the compiler see that, so
+  // the branches here and on the result are plain jumps, not two masked
+  // halves it has to assume may both be skipped
+  const bool vec = __builtin_amdgcn_readfirstlane((int)(vb != nullptr && pw + 64 * V <= lim)) != 0;
+  if (vec) {
+#pragma unroll
+    for (int k = 0; k < V / EV; ++k) {
+      const u32x4 u = gload((const u32x4*)(vb + p - d + k * EV));
+      __builtin_memcpy(&v[k * EV], &u, 16);
+    }
+    if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+      for (int j = 0; j < kTileEx<T>; ++j)
+        if (j < d) ex[j] = gload(vb + p + V - d + j);
+    }
+    return d != 0;
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) v[i] = (p + i < lim) ? src_at(s, p + i) : T(0);
+  return false;
+}
+
+// v[i] = input p + i from the vectors run_issue loaded at p - D: the D
+// inputs that cross into the next lane come from it by one shuffle each
+// (lane 63: from ex).
+template <class T, int D>
+__device__ __forceinline__ void shift_in(T (&v)[kTileV], const T (&ex)[kTileEx<T>]) {
+  constexpr int V = kTileV;
   T nb[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) nb[j] = shdn(raw[j], 1, 64);
+  for (int j = 0; j < D; ++j) nb[j] = shdn(v[j], 1, 64);
 #pragma unroll
-  for (int i = 0; i < V - D; ++i) v[i] = raw[i + D];
-  if ((threadIdx.x & 63) == 63) {
+  for (int i = 0; i < V - D; ++i) v[i] = v[i + D];
+  const bool last = (threadIdx.x & 63) == 63;
 #pragma unroll
-    for (int i = V - D; i < V; ++i) v[i] = gload(vb + p + i);
-  } else {
-#pragma unroll
-    for (int i = V - D; i < V; ++i) v[i] = nb[i - (V - D)];
+  for (int i = V - D; i < V; ++i) v[i] = last ? ex[i - (V - D)] : nb[i - (V - D)];
+}
+
+template <class T>
+__device__ __forceinline__ void run_fix(int d, T (&v)[kTileV], const T (&ex)[kTileEx<T>]) {
+  constexpr int EV = 16 / (int)sizeof(T);
+  switch (d) {
+    case 1: shift_in<T, 1>(v, ex); break;
+    case 2: if constexpr (EV > 2) shift_in<T, 2>(v, ex); break;
+    case 3: if constexpr (EV > 3) shift_in<T, 3>(v, ex); break;
+    case 4: if constexpr (EV > 4) shift_in<T, 4>(v, ex); break;
+    case 5: if constexpr (EV > 5) shift_in<T, 5>(v, ex); break;
+    case 6: if constexpr (EV > 6) shift_in<T, 6>(v, ex); break;
+    case 7: if constexpr (EV > 7) shift_in<T, 7>(v, ex); break;
+    default: break;
   }
 }
 
@@ -204,37 +273,6 @@ __device__ __forceinline__ void store_shifted(T* out, const T (&o)[kTileV]) {
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < D; ++i) gstore(out + i, o[i]);
-  }
-}
-
-// Load the 8 inputs at positions p .. p+7 (those >= lim read as 0, never
-// used).  vb: the segment base (element i at vb + i) or null; d: the
-// misalignment of vb + p in elements.
-template <class T>
-__device__ __forceinline__ void run_load(const Series<T>& s, const T* vb, int d, int64_t p, int64_t lim,
-                                         T (&v)[kTileV]) {
-  constexpr int V = kTileV, EV = 16 / (int)sizeof(T);
-  const int64_t pw = p - (int64_t)(threadIdx.x & 63) * V;  // the wavefront's first position
-  if (vb != nullptr && pw + 64 * V <= lim) {
-    switch (d) {
-      case 0:
-#pragma unroll
-        for (int k = 0; k < V / EV; ++k) {
-          const u32x4 u = gload((const u32x4*)(vb + p + k * EV));
-          __builtin_memcpy(&v[k * EV], &u, 16);
-        }
-        break;
-      case 1: load_shifted<T, 1>(vb, p, v); break;
-      case 2: if constexpr (EV > 2) load_shifted<T, 2>(vb, p, v); break;
-      case 3: if constexpr (EV > 3) load_shifted<T, 3>(vb, p, v); break;
-      case 4: if constexpr (EV > 4) load_shifted<T, 4>(vb, p, v); break;
-      case 5: if constexpr (EV > 5) load_shifted<T, 5>(vb, p, v); break;
-      case 6: if constexpr (EV > 6) load_shifted<T, 6>(vb, p, v); break;
-      default: if constexpr (EV > 7) load_shifted<T, 7>(vb, p, v); break;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = (p + i < lim) ? src_at(s, p + i) : T(0);
   }
 }
 
@@ -327,12 +365,21 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
   const int dout = dmx >= 0 ? dmx : dmn;
   const bool last_run = R1 == nout;
 
-  T cur[V], nxt[V];
+  T cur[V], nxt[V], ex[kTileEx<T>];
   E hx[LAG][V], hn[LAG][V];  // SUF of P_{k-1} (index 0) .. P_{k-LAG}
-  run_load<T>(s, vbase, din, R0 + tid * V, lim, cur);
+  // the first sub-tile is waited for before the loop, whose body cannot
+  // tell these loads from its own prefetch and would wait for both
+  const bool fix0 = run_issue<T>(s, vbase, din, R0 + tid * V, lim, cur, ex);
+#pragma unroll
+  for (int i = 0; i < V; ++i) settle(cur[i]);
+#pragma unroll
+  for (int j = 0; j < kTileEx<T>; ++j) settle(ex[j]);
+  if (__builtin_amdgcn_readfirstlane((int)fix0) != 0) run_fix<T>(din, cur, ex);
   for (int k = 0; k < nsub; ++k) {
     const int pr0 = k * TT + tid * V;  // position of cur[0], relative to R0
-    if (k + 1 < nsub) run_load<T>(s, vbase, din, R0 + pr0 + TT, lim, nxt);
+    bool nfix = false;
+    if (k + 1 < nsub) nfix = run_issue<T>(s, vbase, din, R0 + pr0 + TT, lim, nxt, ex);
+    nfix = __builtin_amdgcn_readfirstlane((int)nfix) != 0;  // uniform: a jump, not masked halves
     if (s.carry != nullptr && last_run) {
       // the series' last w-1 inputs are the next push's carry
 #pragma unroll
@@ -475,6 +522,14 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       }
       __syncthreads();  // PRE of P_k visible
     }
+    // The next sub-tile's inputs are waited for here, on every path (a wait
+    // the compiler could see skipped would land after the stores, and one
+    // counter covers loads and stores: it would wait for them too).
+#pragma unroll
+    for (int i = 0; i < V; ++i) settle(nxt[i]);
+#pragma unroll
+    for (int j = 0; j < kTileEx<T>; ++j) settle(ex[j]);
+    if (nfix) run_fix<T>(din, nxt, ex);
     if (k >= LAG) {
       // windows starting in P_{k-LAG}: SUF (registers), PRE at the window
       // end and the whole block strictly inside, if any (both from the ring;
@@ -541,7 +596,11 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       }
       cur[i] = nxt[i];
     }
-    __syncthreads();  // ring slots of P_{k-1} may now be reused by P_{k+1}
+    // Let this sub-tile's stores complete before the next one's loads are
+    // issued: on MI355X 3-6% faster per launch than leaving them in flight
+    // with the next loads at one or two sub-tiles of lag, even at four.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt untouched
+    lds_barrier();  // ring slots of P_{k-1} may now be reused by P_{k+1}
   }
 }
 
