@@ -137,18 +137,20 @@ bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols, bool one_output) {
 bool stream_cols_2d(int dtype, int64_t w_rows) { return w_rows < 16 || (dsize(dtype) == 2 && w_rows <= 64); }
 
 // Long windows of a single series (more than one chunk per block): the
-// two-pass column kernels, except full 4096-element chunks with at most 16
-// per block, where the look-back kernel was as fast or faster.  On MI355X
-// (n = 2^28 float32), columns / look-back: w = 4097 1.80 / 2.24 ms, 5000
-// 1.14 / 1.98, 6500 1.59 / 1.73, 8192 1.04 / 0.83, 16384 1.02 / 0.85,
-// 65536 0.98 / 0.97, 131072 0.89 / 1.04, 200000 1.29 / 2.03, 2^20 0.95 /
-// 0.99.  MAXMIN_LONG_LOOKBACK=1 / =0 forces either (experiments, tests).
+// two-pass column kernels, except full 4096-element chunks with at most 8
+// per block, where the look-back kernel was faster.  On MI355X (n = 2^28
+// float32), columns (4096-element chunks) / look-back: w = 4097 1.80 / 2.24
+// ms, 5000 1.14 / 1.98, 6500 1.59 / 1.73, 8192 1.04 / 0.83, 16384 1.02 /
+// 0.85, 65536 0.98 / 0.97, 131072 0.89 / 1.04, 200000 1.29 / 2.03, 2^20
+// 0.95 / 0.99; with 2048-element chunks the columns took 0.96 ms at 16384
+// and 0.94 ms at 65536 (long_chunk_max).  MAXMIN_LONG_LOOKBACK=1 / =0
+// forces either (experiments, tests).
 bool long_lookback(int64_t w) {
   const char* e = getenv("MAXMIN_LONG_LOOKBACK");
   if (e && !strcmp(e, "1")) return true;
   if (e && !strcmp(e, "0")) return false;
   const int64_t K = (w + mm::kChunkMax - 1) / mm::kChunkMax, C = (w + K - 1) / K;
-  return C == mm::kChunkMax && K <= 16;
+  return C == mm::kChunkMax && K <= 8;
 }
 
 // Which tile kernel a single series or a row pass of window w runs.
@@ -345,7 +347,7 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     Workspace* ws = nullptr;
     int r = get_ws(st, &ws);
     if (r) return r;
-    const int64_t nch = mm::chunk_count(a.n, a.w);
+    const int64_t nch = mm::chunk_count(a.n, a.w, mm::long_chunk_max(a.w));
     if ((r = ensure_buf(ws, &ws->agg, &ws->agg_bytes, (size_t)std::max<int64_t>(1, 2 * nch) * dsize(dt)))) return r;
     e = mm::launch_long(dt, a, ws->agg, st);
   } else {

@@ -982,9 +982,9 @@ __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const F
 // again from memory and waits on the records of the K-1 chunks before it.
 
 // The raw inputs of chunk slots [r0, r0 + V) (slots >= len read as 0).
-template <class T>
-__device__ __forceinline__ void col_load(const Series<T>& s, int64_t p0, int len, T (&v)[kChunkV]) {
-  constexpr int V = kChunkV, EV = 16 / (int)sizeof(T);
+template <class T, int V>
+__device__ __forceinline__ void col_load(const Series<T>& s, int64_t p0, int len, T (&v)[V]) {
+  constexpr int EV = 16 / (int)sizeof(T);
   const int r0 = threadIdx.x * V;
   const T* pa = nullptr;
   if (p0 + len <= s.na) pa = s.a;
@@ -1001,20 +1001,21 @@ __device__ __forceinline__ void col_load(const Series<T>& s, int64_t p0, int len
   }
 }
 
-template <class T>
+// V: positions per thread, chunks of at most kChunkThreads * V inputs.
+template <class T, int V>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk_agg(Series<T> s, T* aggx, T* aggn) {
-  constexpr int V = kChunkV;
+  constexpr int64_t CM = int64_t(kChunkThreads) * V;
   __shared__ T red[2][kChunkThreads / 64];
   const int64_t w = s.w, n = s.n;
-  const int64_t K = (w + kChunkMax - 1) / kChunkMax, C = (w + K - 1) / K;
-  const int64_t nch = chunk_count(n, w);
+  const int64_t K = (w + CM - 1) / CM, C = (w + K - 1) / K;
+  const int64_t nch = chunk_count(n, w, CM);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t t = blockIdx.x; t < nch; t += gridDim.x) {
     const int64_t b = t / K, k = t - b * K;
     const int64_t p0 = b * w + k * C;
     const int len = (int)min(min(C, w - k * C), n - p0);
     T v[V];
-    col_load<T>(s, p0, len, v);
+    col_load<T, V>(s, p0, len, v);
     T mx = Lim<T>::lo(), mn = Lim<T>::hi();
 #pragma unroll
     for (int i = 0; i < V; ++i)
@@ -1044,14 +1045,21 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_agg(Series<T> s, T* agg
   }
 }
 
-template <class T>
+template <class T, int V> struct ColLds {
+  T xs[lds_len<T>(kChunkThreads * V)];  // staged max outputs
+  T hs[lds_len<T>(kChunkThreads * V)];  // staged min outputs
+  T red[4][kChunkThreads / 64];         // per-wave scan totals
+  T dep[4];                             // PRE-side and SUF-side aggregates
+};
+
+template <class T, int V>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk_col(Series<T> s, const T* aggx, const T* aggn) {
-  constexpr int V = kChunkV;
-  __shared__ ChunkLds<T> sm;
+  constexpr int64_t CM = int64_t(kChunkThreads) * V;
+  __shared__ ColLds<T, V> sm;
   __shared__ T edge[kChunkThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t w = s.w, n = s.n;
-  const int64_t K = (w + kChunkMax - 1) / kChunkMax, C = (w + K - 1) / K;
+  const int64_t K = (w + CM - 1) / CM, C = (w + K - 1) / K;
   const int64_t NB = (n + w - 1) / w;  // blocks, the last one partial
   const int64_t k = blockIdx.x % K, R = gridDim.x / K, rr = blockIdx.x / K;
   const int64_t per = (NB + R - 1) / R;
@@ -1060,8 +1068,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col(Series<T> s, const 
   const int r0 = tid * V;
   T prev[V], cur[V];  // raw inputs of the column's previous chunk and of this one
   if (b0 >= b1 || b0 * w + k * C >= n) return;
-  if (b0 >= 1) col_load<T>(s, (b0 - 1) * w + k * C, lenfull, prev);  // whole: it ends before block b0
-  col_load<T>(s, b0 * w + k * C, (int)min((int64_t)lenfull, n - (b0 * w + k * C)), cur);
+  if (b0 >= 1) col_load<T, V>(s, (b0 - 1) * w + k * C, lenfull, prev);  // whole: it ends before block b0
+  col_load<T, V>(s, b0 * w + k * C, (int)min((int64_t)lenfull, n - (b0 * w + k * C)), cur);
   for (int64_t b = b0; b < b1; ++b) {
     const int64_t p0 = b * w + k * C;
     if (p0 >= n) break;
@@ -1069,7 +1077,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col(Series<T> s, const 
     // the next chunk's loads fly while this one is computed
     T nxt[V];
     const int64_t p1 = p0 + w;
-    if (b + 1 < b1 && p1 < n) col_load<T>(s, p1, (int)min((int64_t)lenfull, n - p1), nxt);
+    if (b + 1 < b1 && p1 < n) col_load<T, V>(s, p1, (int)min((int64_t)lenfull, n - p1), nxt);
     // the aggregates this chunk needs, loaded now so their latency hides
     // behind the scans: (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
     const bool has_out = (p0 + len - 1) >= (w - 1);
@@ -1855,9 +1863,26 @@ int grid_cap(int dtype, int strategy) {
   return c;
 }
 
+template <class T, int V>
+static hipError_t launch_long_v(const Series<T>& s, int64_t nch, int64_t K, T* ax, T* an, hipStream_t st) {
+  const int g1 = (int)std::min<int64_t>(nch, (int64_t)cu_count() * 8);
+  hipLaunchKernelGGL((k_chunk_agg<T, V>), dim3(g1), dim3(kChunkThreads), 0, st, s, ax, an);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // whole columns per workgroup group: a multiple of K workgroups (no
+  // workgroup waits on another, so the grid may exceed residency)
+  const int64_t cap = occupancy_grid(k_chunk_col<T, V>, kChunkThreads);
+  const int64_t g2 = std::max<int64_t>(1, cap / K) * K;
+  if (g2 > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_chunk_col<T, V>), dim3((unsigned)g2), dim3(kChunkThreads), 0, st, s, (const T*)ax,
+                     (const T*)an);
+  return hipGetLastError();
+}
+
 hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st) {
-  const int64_t K = (a.w + kChunkMax - 1) / kChunkMax;
-  const int64_t nch = chunk_count(a.n, a.w);
+  const int64_t cmax = long_chunk_max(a.w);
+  const int64_t K = (a.w + cmax - 1) / cmax;
+  const int64_t nch = chunk_count(a.n, a.w, cmax);
   if (nch <= 0) return hipSuccess;
   if (K < 2 || a.mode != kJobOne) return hipErrorInvalidValue;
   return dispatch(dtype, [&](auto* p) {
@@ -1865,18 +1890,8 @@ hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st) {
     const Series<T> s = make_series<T>(a);
     T* ax = (T*)agg;
     T* an = ax + nch;
-    const int g1 = (int)std::min<int64_t>(nch, (int64_t)cu_count() * 8);
-    hipLaunchKernelGGL(k_chunk_agg<T>, dim3(g1), dim3(kChunkThreads), 0, st, s, ax, an);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // whole columns per workgroup group: a multiple of K workgroups (no
-    // workgroup waits on another, so the grid may exceed residency)
-    const int64_t cap = occupancy_grid(k_chunk_col<T>, kChunkThreads);
-    const int64_t g2 = std::max<int64_t>(1, cap / K) * K;
-    if (g2 > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chunk_col<T>, dim3((unsigned)g2), dim3(kChunkThreads), 0, st, s, (const T*)ax,
-                       (const T*)an);
-    return hipGetLastError();
+    return long_col_v(a.w) == kColVShort ? launch_long_v<T, kColVShort>(s, nch, K, ax, an, st)
+                                         : launch_long_v<T, kChunkV>(s, nch, K, ax, an, st);
   });
 }
 

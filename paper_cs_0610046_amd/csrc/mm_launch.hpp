@@ -72,14 +72,29 @@ inline int64_t run_length(int64_t nout, int64_t grid, int64_t cap = kTileRunMax)
   r = r < kTileOut ? kTileOut : r;
   return r > cap ? cap : r;
 }
-// Number of chunk tiles covering [0, n) for window w (0 if n < w: no output).
-__host__ __device__ inline int64_t chunk_count(int64_t n, int64_t w) {
+// Number of chunk tiles covering [0, n) for window w (0 if n < w: no output),
+// chunks of at most cmax inputs.
+__host__ __device__ inline int64_t chunk_count(int64_t n, int64_t w, int64_t cmax = kChunkMax) {
   if (n < w || n <= 0) return 0;
-  int64_t K = (w + kChunkMax - 1) / kChunkMax;
+  int64_t K = (w + cmax - 1) / cmax;
   int64_t C = (w + K - 1) / K;
   int64_t last = n - 1;
   return (last / w) * K + (last % w) / C + 1;
 }
+// Chunk size of the two-pass long-window kernels: chunks of at most 2048
+// (eight positions per thread, five workgroups per CU instead of three)
+// where that measured faster on MI355X (n = 2^28 float32), else of 4096:
+// up to w = 65536 for blocks of whole 4096-element chunks or of at most
+// three chunks.  2048 / 4096: w = 9000 1.06 / 1.07 ms, 10000 1.00 / 1.24,
+// 65536 0.94 / 0.97, but 40000 0.98 / 0.94, 262144 0.99 / 0.86 and 2^20
+// 1.17 / 0.94.
+constexpr int kColVShort = 8;
+inline int long_col_v(int64_t w) {
+  const int64_t K = (w + kChunkMax - 1) / kChunkMax;
+  const bool whole = K * kChunkMax == w;
+  return w <= 65536 && (whole || K <= 3) ? kColVShort : kChunkV;
+}
+inline int64_t long_chunk_max(int64_t w) { return int64_t(kChunkThreads) * long_col_v(w); }
 
 // Type-erased description of a 1-D launch (converted to Job<T> inside).
 struct JobArgs {
@@ -133,8 +148,9 @@ int grid_cap(int dtype, int strategy);
 
 hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st);
 // Single series (a.mode 0) with more than one chunk per block of w: chunk
-// aggregates into agg (2 * chunk_count(n, w) elements), then one column of
-// chunks per workgroup (no look-back, no re-read of the chunk w back).
+// aggregates into agg (2 * chunk_count(n, w, long_chunk_max(w)) elements),
+// then one column of chunks per workgroup (no look-back, no re-read of the
+// chunk w back).
 hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st);
 
 // Batched setup: fills S descriptors (bytes: S * series_bytes()) and the
