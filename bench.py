@@ -2,9 +2,10 @@
 
 A step is one pass of the hot path over the n = 2**28 float32 random-walk
 series: the running max and min at each of the windows 16, 256, 4096 and
-65536 (four launches; the tile kernel serves the first three -- its
-instantiation for windows over one sub-tile at w = 4096 -- and the chunk
-kernel the last).  ``value`` is input elements processed per second over
+65536 (the tile kernel serves the first three -- its instantiation for
+windows over one sub-tile at w = 4096 -- and the two chunk passes, chunk
+aggregates then columns of chunks, the last).  ``value`` is input elements
+processed per second over
 the K timed steps (Gelem/s), inputs already resident in HBM.
 
 Also reported on the same JSON line (not part of ``value``):
@@ -48,7 +49,8 @@ def alg_bytes(n, w, s):
 
 def kernel_name(strategy, w):
     # as rocprofv3 names the single-series float32 instantiations (the tile
-    # kernel's last template argument: windows end one or two sub-tiles on)
+    # kernel's last template argument: windows end one or two sub-tiles on);
+    # longer windows: the chunk kernels (a label; they are never dominant here)
     if strategy == "tile":
         return "mm::k_tile<0, float, false, %d>" % (1 if w <= 2048 else 2)
     return "mm::k_%s<0, float>" % strategy
