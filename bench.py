@@ -5,8 +5,8 @@ series: the running max and min at each of the windows 16, 256, 4096 and
 65536 (the tile kernel serves the first three -- its instantiation for
 windows over one sub-tile at w = 4096 -- and the two chunk passes, chunk
 aggregates then columns of chunks, the last).  ``value`` is input elements
-processed per second over
-the K timed steps (Gelem/s), inputs already resident in HBM.
+processed per second over the K timed steps (Gelem/s), inputs already
+resident in HBM.
 
 Also reported on the same JSON line (not part of ``value``):
 * ``per_window``   -- each window's launch time, Gelem/s and % of 8 TB/s
