@@ -133,8 +133,10 @@ def test_large_windows(strategy, lookback, monkeypatch):
         check(a, w, "w=%d" % w, strategy=strategy)
     if strategy == mm.STRATEGY_AUTO:
         for dt in DTS:
-            for w, n in ((4097, 4097), (4097, 3 * 4097 + 5), (8192, 8192 * 7 + 4095), (12289, 12289 * 5 + 1),
-                         (20000, 20000 * 30 + 19999), (1 << 20, (1 << 20) + 77)):
+            # 10000 and 65536: the two-pass kernels with 2048-element chunks
+            for w, n in ((4097, 4097), (4097, 3 * 4097 + 5), (8192, 8192 * 7 + 4095), (10000, 10000 * 6 + 123),
+                         (12289, 12289 * 5 + 1), (20000, 20000 * 30 + 19999), (65536, 65536 * 3 + 5),
+                         (1 << 20, (1 << 20) + 77)):
                 b = gen(n, dt, rng, "walk" if w % 2 else "ties")
                 note("large-w dt=%s n=%d w=%d lookback=%s" % (np.dtype(dt).name, n, w, lookback))
                 check(b, w, "dt=%s n=%d w=%d" % (np.dtype(dt).name, n, w))
