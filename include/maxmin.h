@@ -57,7 +57,7 @@ typedef enum {
 typedef enum {
   MAXMIN_STRATEGY_AUTO = 0,  /* planner / autotuner decides */
   MAXMIN_STRATEGY_TILE = 1,  /* LDS tile: power-of-two block prefix/suffix plus whole blocks between (w <= 8192; series of a batched call: w <= 2048) */
-  MAXMIN_STRATEGY_CHUNK = 2, /* window-aligned chunks, cross-workgroup look-back over chunk aggregates (any w) */
+  MAXMIN_STRATEGY_CHUNK = 2, /* window-aligned chunks: cross-workgroup look-back over chunk aggregates, or (one series, most windows of several chunks) chunk aggregates first, then columns of chunks (any w) */
   MAXMIN_STRATEGY_RUN = 3    /* window-aligned chunks walked in runs, aggregates kept per workgroup (any w) */
 } maxmin_strategy_t;
 
