@@ -10,10 +10,16 @@ resident in HBM.
 
 Also reported on the same JSON line (not part of ``value``):
 * ``per_window``   -- each window's launch time, Gelem/s and % of 8 TB/s
-  (algorithmic bytes: n*s read + 2*(n-w+1)*s written),
+  (algorithmic bytes: n*s read + 2*(n-w+1)*s written) and of the measured
+  copy ceiling,
 * ``roofline``     -- the dominant kernel (most time per step) against HBM
-  peak, with its measured HBM traffic per launch when the committed counter
-  summary matches the current kernel sources,
+  peak and against the measured copy ceiling, with its measured HBM traffic
+  per launch when the committed counter summary matches the current kernel
+  sources,
+* ``ceiling``      -- the device's practical HBM ceiling: a 4 GiB device copy
+  and fill (``--ceiling`` runs only this),
+* ``large_other``  -- the rest of the n = 2**28 workload: float32 piecewise
+  monotone and ramp, the float64 copy of the walk, int32 uniform,
 * ``plain``        -- n = 2**20 float32, w = 64 (latency-bound),
 * ``batched``      -- 10,000 float32 random walks, lengths log-uniform in
   [1e3, 1e6], windows uniform in [2, 1024], one batched call (graph replay),
@@ -23,7 +29,9 @@ Also reported on the same JSON line (not part of ``value``):
 * ``max_only``     -- the same walk, w = 256, only the max output,
 * ``envelope``     -- centered envelopes of 100,000 walks of 1024 samples,
 * ``morphology``   -- opening of the 8192 x 8192 field with a 15 x 15 square,
-* ``cpu_baseline`` -- the CPU oracle (single thread) on a bounded sample.
+* ``cpu_baseline`` -- the CPU oracle (single thread) on a bounded sample, with
+  the host's CPU model and core counts; ``batched.cpu_oracle_parallel`` is
+  the oracle over the batch's series on up to 16 host threads.
 """
 import argparse
 import json
@@ -48,12 +56,16 @@ def alg_bytes(n, w, s):
 
 
 def kernel_name(strategy, w):
-    # as rocprofv3 names the single-series float32 instantiations (the tile
-    # kernel's last template argument: windows end one or two sub-tiles on);
-    # longer windows: the chunk kernels (a label; they are never dominant here)
+    """The kernel(s) rocprofv3 names for a single-series float32 launch: the
+    tile kernel (last template argument: how many sub-tiles after its start
+    a window may end), or for w > 8192 the two long-window passes (chunk
+    aggregates, then columns of chunks; 2048-element chunks where the
+    planner picks them, else 4096)."""
     if strategy == "tile":
-        return "mm::k_tile<0, float, false, %d>" % (1 if w <= 2048 else 2)
-    return "mm::k_%s<0, float>" % strategy
+        return "mm::k_tile<0, float, false, %d>" % (1 if w <= 2048 else (w + 2047) // 2048)
+    k = (w + 4095) // 4096
+    v = 8 if w <= 65536 and (k * 4096 == w or k <= 3) else 16
+    return "mm::k_chunk_agg<float, %d> + mm::k_chunk_col<float, %d>" % (v, v)
 
 
 # Sources whose change invalidates counter-derived traffic figures.
@@ -93,6 +105,44 @@ def measured_traffic(kernel, n):
     return vals[kernel], TRAFFIC_FILE
 
 
+def measure_ceiling(torch, dev, stream, gib=4, iters=10):
+    """Practical HBM ceiling on this device: a device-to-device copy of
+    ``gib`` GiB (each byte read once and written once) and a fill of the
+    same buffer (written once), both far larger than the last-level cache,
+    timed with events on the launch stream (median of ``iters``)."""
+    nbytes = gib << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    tc = float(np.median(timed(lambda: dst.copy_(src), iters, stream)))
+    tf = float(np.median(timed(lambda: dst.fill_(2.0), iters, stream)))
+    del src, dst
+    return {"copy_GBs": round(2 * nbytes / (tc * 1e-3) / 1e9, 1), "copy_ms": round(tc, 4),
+            "fill_GBs": round(nbytes / (tf * 1e-3) / 1e9, 1), "fill_ms": round(tf, 4),
+            "buffer_bytes": nbytes,
+            "what": "torch device copy (read + write) and fill (write) of %d GiB float32 buffers, median of %d "
+                    "event-timed calls" % (gib, iters)}
+
+
+def host_cpu():
+    """Host CPU model and core counts (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def timed(fn, iters, stream):
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
@@ -115,6 +165,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="measure the planner's launch parameters first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (a known-size kernel for counter calibration)")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="only measure the device's copy / fill bandwidth (4 GiB buffers) and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the benchmark runs on one GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -132,6 +184,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.ceiling:
+        print(json.dumps({"ceiling": measure_ceiling(torch, dev, stream)}), flush=True)
+        return
     tuning = mm.maxmin_tuning(torch.float32)
     if args.autotune:
         t0 = time.time()
@@ -200,10 +255,16 @@ def main():
                 "avg_launch_ms": round(dom_ms, 4)}
     print("[bench] headline %.1f Gelem/s, %.3f ms/step" % (value, ms_per_step), file=sys.stderr, flush=True)
     del outs
+    ceiling = measure_ceiling(torch, dev, stream)
+    cgb = ceiling["copy_GBs"]
+    for w in WINDOWS:
+        per_window[str(w)]["pct_copy_ceiling"] = round(100 * per_window[str(w)]["alg_GBs"] / cgb, 1)
+    roofline["frac_of_copy_ceiling"] = round(achieved / cgb, 4)
+    print("[bench] ceiling copy %.0f GB/s fill %.0f GB/s" % (cgb, ceiling["fill_GBs"]), file=sys.stderr, flush=True)
 
     extras = {}
     if args.extras:
-        extras = run_extras(torch, mm, synth, dev, stream)
+        extras = run_extras(torch, mm, synth, dev, stream, cgb)
 
     # CPU oracle on a bounded sample of the same workload (rank 0, N=1 only)
     import oracle
@@ -214,7 +275,8 @@ def main():
     ct = time.perf_counter() - t0
     cpu = {"value": round(len(WINDOWS) * m / ct / 1e9, 5), "unit": "Gelem/s", "cores": 1, "kind": "oracle",
            "sample": "first 2^%d elements of the same float32 walk, windows %s, one thread (g++ -O2 "
-                     "monotonic-wedge oracle), %.1f s" % (args.cpu_sample_log2, list(WINDOWS), ct)}
+                     "monotonic-wedge oracle), %.1f s" % (args.cpu_sample_log2, list(WINDOWS), ct),
+           "host": host_cpu()}
 
     line = {"metric": "Gelem/s and % HBM peak, batched vs plain kernel; serving p50/p99 latency",
             "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1, "steps": args.steps,
@@ -222,13 +284,73 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "single float32 random walk n=2^%d, windows %s" % (args.n_log2, list(WINDOWS)),
                        "n": n, "windows": list(WINDOWS)},
-            "per_window": per_window, "roofline": roofline, "cpu_baseline": cpu, "tuning": tuning}
+            "per_window": per_window, "roofline": roofline, "ceiling": ceiling, "cpu_baseline": cpu,
+            "tuning": tuning}
     line.update(extras)
     print(json.dumps(line), flush=True)
 
 
-def run_extras(torch, mm, synth, dev, stream):
+def batched_cpu_parallel(packed, offs, wins, target=1 << 29):
+    """The CPU oracle on the batched workload, series in parallel on the
+    host's cores (at most 16 threads: one GPU's share of the host), over the
+    first series that hold about ``target`` elements."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    k = int(np.searchsorted(offs, min(target, int(offs[-1])))) or 1
+    threads = max(1, min(16, host_cpu()["usable_cpus"]))
+
+    def run(i):
+        oracle.wedge(packed[offs[i]:offs[i + 1]], int(wins[i]))
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, range(k)))
+    ct = time.perf_counter() - t0
+    m = int(offs[k])
+    return {"value": round(m / ct / 1e9, 4), "unit": "Gelem/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of the 10,000 series (%d elements), one series per task on %d threads, %.1f s" %
+                      (k, m, threads, ct)}
+
+
+def run_extras(torch, mm, synth, dev, stream, copy_gbs):
     out = {}
+    # the rest of the n = 2^28 single-series workload: the other float32
+    # inputs, and the float64 and int32 copies (same windows; not in `value`)
+    others = {}
+    for key, make, tdt, s in (
+            ("f32_piecewise_monotone", lambda: synth.large_series("pwm"), torch.float32, 4),
+            ("f32_ramp", lambda: synth.large_series("ramp"), torch.float32, 4),
+            ("f64_walk", lambda: synth.random_walk(1 << 28, np.float64, synth.rng_for("large", 0)), torch.float64, 8),
+            ("i32_uniform", lambda: synth.large_series("i32"), torch.int32, 4)):
+        t0 = time.time()
+        h = make()
+        xo = torch.from_numpy(h).to(dev)
+        del h
+        n = xo.numel()
+        res = {}
+        for w in WINDOWS:
+            o1 = torch.empty(n - w + 1, dtype=tdt, device=dev)
+            o2 = torch.empty_like(o1)
+            for _ in range(2):
+                mm.maxmin_filter(xo, w, o1, o2)
+            ts = timed(lambda: mm.maxmin_filter(xo, w, o1, o2), 10, stream)
+            ms = float(np.median(ts))
+            gb = alg_bytes(n, w, s) / (ms * 1e-3) / 1e9
+            res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                           "pct_hbm": round(100 * gb / HBM_PEAK_GBS, 1),
+                           "pct_copy_ceiling": round(100 * gb / copy_gbs, 1)}
+            del o1, o2
+        mm.maxmin_check_stream()
+        step_ms = sum(r["ms"] for r in res.values())
+        others[key] = {"per_window": res, "step_ms": round(step_ms, 4),
+                       "gelem_s": round(len(WINDOWS) * n / (step_ms * 1e-3) / 1e9, 2)}
+        print("[bench] %s %.3f ms per step of 4 windows (%.1fs)" % (key, step_ms, time.time() - t0),
+              file=sys.stderr, flush=True)
+        del xo
+    out["large_other"] = {"workload": "n=2^28 single series, windows %s: float32 piecewise monotone and ramp, "
+                                      "float64 walk, int32 uniform (algorithmic bytes n*s + 2*(n-w+1)*s; "
+                                      "median of 10 event-timed launches per window)" % list(WINDOWS),
+                          "per_input": others}
     # plain: n = 2^20 float32 uniform, w = 64
     a = synth.uniform01(1 << 20)
     x = torch.from_numpy(a).to(dev)
@@ -251,6 +373,7 @@ def run_extras(torch, mm, synth, dev, stream):
           flush=True)
     oo = mm.maxmin_out_offsets(offs, wins)
     xb = torch.from_numpy(packed).to(dev)
+    cpu_par = batched_cpu_parallel(packed, offs, wins)
     del packed
     d_off, d_w, d_oo = (torch.from_numpy(v).to(dev) for v in (offs, wins, oo))
     total = int(oo[-1])
@@ -267,7 +390,9 @@ def run_extras(torch, mm, synth, dev, stream):
     ab = N * 4 + 2 * total * 4
     out["batched"] = {"workload": "10000 float32 walks, n log-uniform [1e3,1e6], w uniform [2,1024], graph replay",
                       "elements": N, "ms": round(ms, 4), "gelem_s": round(N / (ms * 1e-3) / 1e9, 2),
-                      "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
+                      "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
+                      "pct_copy_ceiling": round(100 * ab / (ms * 1e-3) / 1e9 / copy_gbs, 1),
+                      "cpu_oracle_parallel": cpu_par}
     print("[bench] batched %.3f ms" % ms, file=sys.stderr, flush=True)
     del xb, bmx, bmn
 

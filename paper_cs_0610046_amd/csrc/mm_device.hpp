@@ -30,11 +30,12 @@ template <> struct Lim<uint16_t> {
 template <class T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
 template <class T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
 // hmax / hmin: the same selection through the hardware max/min instruction
-// for floating types.  For the inputs the library accepts -- no NaN, no
-// -0.0 -- v_max / v_min return one operand's bits unchanged, exactly as the
-// compare-select does: the larger (smaller) value, and equal values have
-// equal bits; denormals pass through (the kernels run with FP32/FP64
-// denormals preserved).  Written as one instruction each: through the
+// for floating types.  For the inputs the library accepts (NaN-free; +-inf,
+// subnormals and -0.0 allowed) v_max / v_min return one operand's bits
+// unchanged, exactly as the compare-select does: the larger (smaller)
+// value, and equal values other than +0.0 / -0.0 have equal bits (a window
+// holding both zeros may return either, as the ABI states); denormals pass
+// through (the kernels run with FP32/FP64 denormals preserved).  Written as one instruction each: through the
 // compiler's maxnum the same instruction comes with a canonicalising max of
 // every loaded or shuffled operand, which cost more than it saved in the
 // tile kernel.  On MI355X (n = 2^28 float32) this took the tile kernel from

@@ -230,3 +230,64 @@ def request_payload(dtype, n, seed):
     if dtype == np.int32:
         return uniform_i32(n, rng)
     return random_walk(n, dtype, rng)
+
+
+# ------------------------------------------------------------ edge values
+def _edge_specials(dtype):
+    dtype = np.dtype(dtype)
+    if dtype.kind == "f":
+        fi = np.finfo(dtype)
+        ub = {4: np.uint32, 8: np.uint64}[dtype.itemsize]
+        sub_min = np.array([1], ub).view(dtype)[0]
+        sub_max = np.array([(1 << fi.nmant) - 1], ub).view(dtype)[0]
+        v = [-np.inf, np.inf, -0.0, sub_min, -sub_min, sub_max, -sub_max, fi.tiny, -fi.tiny,
+             fi.max, -fi.max, 1.0, -1.0]
+        return np.array(v, dtype)
+    if dtype == np.int32:
+        return np.array([-2**31, -2**31 + 1, -1, 0, 1, 2**31 - 2, 2**31 - 1], np.int32)
+    if dtype == np.uint16:
+        return np.array([0, 1, 32767, 32768, 65534, 65535], np.uint16)
+    raise ValueError(dtype)
+
+
+def _random_bits(n, dtype, rng):
+    """Values drawn uniformly over the type's bit patterns: for floats every
+    NaN pattern becomes -inf and +0.0 becomes -0.0 (so a window never holds
+    both zeros, whose selected bits the contract leaves unspecified)."""
+    dtype = np.dtype(dtype)
+    if dtype.kind != "f":
+        info = np.iinfo(dtype)
+        return rng.integers(int(info.min), int(info.max) + 1, n, dtype=np.int64).astype(dtype)
+    ub = {4: np.uint32, 8: np.uint64}[dtype.itemsize]
+    bitsv = rng.integers(0, np.iinfo(ub).max, n, dtype=ub, endpoint=True)
+    x = bitsv.view(dtype)
+    x[np.isnan(x)] = -np.inf
+    x[x == 0] = -0.0
+    return x
+
+
+def edge_series(n, dtype, rng, special_frac=0.4):
+    """Series made of the values a selection kernel is most likely to get
+    wrong: +-inf, -0.0 (never +0.0), subnormals, the largest finite and
+    smallest normal values, integer extremes (INT32_MIN/MAX, uint16 0 and
+    65535, i.e. the identities of the running max and min), and values
+    uniform over the type's bit patterns.  Values come in runs: mostly
+    short, some of ~100 and a few of 1000-20000 samples, so whole windows
+    hold a single extreme value.  NaN-free."""
+    dtype = np.dtype(dtype)
+    if n == 0:
+        return np.zeros(0, dtype)
+    runs = []
+    total = 0
+    while total < n:
+        u = rng.random()
+        k = int(rng.geometric(1 / 3.0)) if u < 0.7 else (int(rng.geometric(1 / 100.0)) if u < 0.95
+                                                          else int(rng.integers(1000, 20001)))
+        runs.append(k)
+        total += k
+    runs = np.array(runs, np.int64)
+    spec = _edge_specials(dtype)
+    pick = rng.random(runs.size) < special_frac
+    vals = _random_bits(runs.size, dtype, rng)
+    vals[pick] = spec[rng.integers(0, spec.size, int(pick.sum()))]
+    return np.repeat(vals, runs)[:n].copy()

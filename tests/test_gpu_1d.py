@@ -220,15 +220,18 @@ def test_repeatable_bits():
             assert torch.equal(r[0], r0[0]) and torch.equal(r[1], r0[1])
 
 
-@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000, 7000, 9000, 20000])
+@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000, 7000, 9000, 20000, 40000])
 def test_stream_chunks_equal_one_shot(w, monkeypatch):
-    if w == 20000:  # the look-back chunk kernel for a push too (w = 9000 takes the column kernels)
+    """Every dtype.  w = 9000 takes the two-pass kernels with 2048-element
+    chunks, w = 40000 with 4096-element chunks (k_chunk_col<T, 16>), w =
+    20000 is forced onto the look-back chunk kernel."""
+    if w == 20000:
         monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", "1")
     import torch
     rng = synth.rng_for("tests", 106)
-    for dt in (np.float32, np.float64, np.int32):
-        a = gen(40000, dt, rng, "walk")
-        st = mm.maxmin_stream_create(torch.float32 if dt == np.float32 else (torch.float64 if dt == np.float64 else torch.int32), w)
+    for dt in DTS:
+        a = gen(40000 if w < 40000 else 250000, dt, rng, "walk")
+        st = mm.maxmin_stream_create(to_dev(a[:1]).dtype, w)
         ost = oracle.Stream(dt, w)
         pos = 0
         outs = []
