@@ -136,8 +136,9 @@ int maxmin_out_offsets(const int64_t* h_in_offsets, const int64_t* h_windows, in
  *   must be issued in order on one stream (each reads the carry the
  *   previous one wrote).  Errors: EINVAL (null handle, m < 0, null pointers
  *   with work to do).
- * maxmin_stream_destroy: frees the handle (after synchronising the device
- *   memory it owns).  NULL is accepted.
+ * maxmin_stream_destroy: frees the handle and its device carries after
+ *   waiting for the handle's last push to finish (an event recorded on that
+ *   push's stream; no device-wide synchronisation).  NULL is accepted.
  * maxmin_stream_samples: samples pushed so far (t), or -1 for NULL.
  */
 typedef struct maxmin_stream maxmin_stream_t;
@@ -258,6 +259,15 @@ int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int
  *   receives the request id.  Pushes of one stream complete in order.
  * maxmin_engine_poll: up to `cap` finished requests since the last poll:
  *   ids, n_out (windows written), latency in seconds, status; *got = count.
+ *   Status EDEVICE: the request's batch failed.  If its HIP calls failed, a
+ *   push leaves its stream as it was before the push (the chunk may be
+ *   pushed again).  If the batch's chunk-strategy kernels report a look-back
+ *   wait that gave up (see maxmin_check_stream), every request of the batch
+ *   fails and each stream pushed in it is broken: its later pushes finish
+ *   with EDEVICE (close it and open a new one).
+ *   Tests can force either case: environment MAXMIN_ENGINE_INJECT="launch:K"
+ *   or "err:K" (read at maxmin_engine_create) makes the engine's K-th batch
+ *   fail before enqueuing anything, or report the look-back error word set.
  * maxmin_engine_drain: wait until every submitted request has finished.
  * maxmin_engine_stats: out8 = {submitted, finished, batches, rejected,
  *   samples processed, budget bytes in use, peak bytes in use, pending}.

@@ -317,25 +317,37 @@ int chunk_ranges(int dt, int64_t w) {
   return v;
 }
 
+}  // namespace
+
+namespace mm {
+// One series with the tile kernel (w <= 8192): run length from the tuning
+// table, persistent grid; no scratch memory.
+hipError_t launch_tile_series(int dt, JobArgs a, hipStream_t st) {
+  const int ks = tile_kind(a.w);
+  const int cap = grid_cap(dt, ks);
+  // a run re-reads the w-1 inputs after it: runs 4x longer for windows
+  // over more than one sub-tile (MI355X, n = 2^28 float32, w =
+  // 2049..4096: 64 sub-tiles 0.71-0.73 ms, 32: 0.72-0.73, 16: 0.74-0.75)
+  const int64_t rmax = (int64_t)tuning(dt).tile_run * (ks == kStratTile ? 1 : 4) * kTileOut;
+  a.run = run_length(a.n - a.w + 1, cap, rmax);
+  if (const char* e = getenv("MAXMIN_TILE_RUN")) {
+    const int64_t r = atoll(e) / kTileOut * kTileOut;
+    if (r > 0 && r < a.run) a.run = r;
+  }
+  a.ntiles = run_count(a.n, a.w, a.run);
+  const int grid = (int)std::min<int64_t>(a.ntiles, cap);
+  return launch_1d(dt, ks, a, grid, st);
+}
+}  // namespace mm
+
+namespace {
+
 // Run one 1-D series (plain call or stream push) with the planned strategy.
 int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
   const int strat = plan_strategy(dt, a.n, a.w);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
-    const int ks = tile_kind(a.w);
-    const int cap = mm::grid_cap(dt, ks);
-    // a run re-reads the w-1 inputs after it: runs 4x longer for windows
-    // over more than one sub-tile (MI355X, n = 2^28 float32, w =
-    // 2049..4096: 64 sub-tiles 0.71-0.73 ms, 32: 0.72-0.73, 16: 0.74-0.75)
-    const int64_t rmax = (int64_t)tuning(dt).tile_run * (ks == mm::kStratTile ? 1 : 4) * mm::kTileOut;
-    a.run = mm::run_length(a.n - a.w + 1, cap, rmax);
-    if (const char* e = getenv("MAXMIN_TILE_RUN")) {
-      const int64_t r = atoll(e) / mm::kTileOut * mm::kTileOut;
-      if (r > 0 && r < a.run) a.run = r;
-    }
-    a.ntiles = mm::run_count(a.n, a.w, a.run);
-    const int grid = (int)std::min<int64_t>(a.ntiles, cap);
-    e = mm::launch_1d(dt, ks, a, grid, st);
+    e = mm::launch_tile_series(dt, a, st);
   } else if (strat == MAXMIN_STRATEGY_RUN) {
     a.run = run_chunks_per_run(dt, a.n, a.w);
     a.ntiles = (mm::crun_chunks(a.n, a.w) + a.run - 1) / a.run;
@@ -402,6 +414,7 @@ struct maxmin_stream {
   int device;
   void* carry[2];
   int cur;
+  hipEvent_t last;  // recorded after each push: destroy waits for it, not for the device
 };
 
 extern "C" {
@@ -664,10 +677,13 @@ int maxmin_stream_create(int dtype, int64_t w, maxmin_stream_t** out) {
   hipGetDevice(&st->device);
   const size_t bytes = (size_t)std::max<int64_t>(1, w - 1) * s;
   st->carry[0] = st->carry[1] = nullptr;
+  st->last = nullptr;
   hipError_t e = hipMalloc(&st->carry[0], bytes);
   if (e == hipSuccess) e = hipMalloc(&st->carry[1], bytes);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->last, hipEventDisableTiming);
   if (e != hipSuccess) {
     if (st->carry[0]) hipFree(st->carry[0]);
+    if (st->carry[1]) hipFree(st->carry[1]);
     delete st;
     return fail(MAXMIN_ENOMEM, "maxmin_stream_create: hipMalloc(carry, %zu B): %s", bytes, hipGetErrorString(e));
   }
@@ -706,6 +722,8 @@ int maxmin_stream_push(maxmin_stream_t* st, const void* d_chunk, int64_t m, void
     hipError_t e = mm::launch_carry_only(st->dt, a, hs);
     if (e != hipSuccess) return hip_fail(e, "maxmin_stream_push (carry)");
   }
+  hipError_t e = hipEventRecord(st->last, hs);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_stream_push (event)");
   st->cur = 1 - st->cur;
   st->t += m;
   if (h_n_out) *h_n_out = nout;
@@ -716,10 +734,14 @@ int64_t maxmin_stream_samples(const maxmin_stream_t* st) { return st ? st->t : -
 
 int maxmin_stream_destroy(maxmin_stream_t* st) {
   if (!st) return ok();
-  hipDeviceSynchronize();
+  // the carries may still be read or written by the last push: wait for it
+  // (the event recorded after it), not for the whole device
+  hipError_t e = hipEventSynchronize(st->last);
   hipFree(st->carry[0]);
   hipFree(st->carry[1]);
+  hipEventDestroy(st->last);
   delete st;
+  if (e != hipSuccess) return hip_fail(e, "maxmin_stream_destroy");
   return ok();
 }
 

@@ -23,6 +23,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -110,13 +112,19 @@ struct EStream {
   int cur = 0;       // which carry holds the latest samples
   int lane = 0;
   int64_t queued = 0;  // pushes submitted but not yet completed
+  bool broken = false;  // a push's kernels reported a device error: later pushes fail
 };
+
+// Host slots (pinned) that receive a lane's look-back error word after each
+// batch that ran the chunk kernel.
+constexpr int64_t kErrSlots = 4096;
 
 struct Batch {
   int lane = 0;
   std::vector<Req*> reqs;
   std::vector<char> host;  // host image of the descriptors (kept until completion)
   hipEvent_t ev = nullptr;
+  int64_t slot = -1;  // error-word slot, or -1 when no chunk kernel ran
 };
 
 struct Lane {
@@ -124,6 +132,9 @@ struct Lane {
   std::deque<Batch*> inflight;
   char* desc = nullptr;  // descriptor buffer: batches on one lane run in order, so one suffices
   size_t desc_cap = 0;
+  mm::Ctl* ctl = nullptr;       // the lane stream's look-back control words
+  uint32_t* h_err = nullptr;    // kErrSlots pinned words
+  int64_t next_slot = 0;
 };
 
 }  // namespace
@@ -145,6 +156,10 @@ struct maxmin_engine {
   int64_t n_submitted = 0, n_done = 0, n_batches = 0, n_rejected = 0, elems_done = 0, peak_used = 0;
   int64_t in_system = 0;  // submitted and not yet collected as done
   int64_t reserved = 0;   // budget held by open streams' carries
+  // Fault injection for tests (MAXMIN_ENGINE_INJECT="launch:K" or "err:K"):
+  // the K-th batch launched fails before enqueuing anything, or reports the
+  // look-back error word as set.  0 = off.
+  int64_t inject_launch = 0, inject_err = 0, launch_seq = 0;
 
   void scheduler_loop();
   void poller_loop();
@@ -214,6 +229,10 @@ bool maxmin_engine::admit(Req* r, std::set<int64_t>& used_sids, std::vector<std:
   }
   if (used_sids.count(r->sid)) return false;
   EStream& es = it->second;
+  if (es.broken) {
+    finish(r, MAXMIN_EDEVICE);
+    return true;
+  }
   const int64_t c = std::min(es.t, es.w - 1);
   const int64_t total = c + r->n;
   r->nout = std::max<int64_t>(0, total - es.w + 1);
@@ -246,10 +265,19 @@ bool maxmin_engine::admit(Req* r, std::set<int64_t>& used_sids, std::vector<std:
 
 void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
   Lane& L = lanes[lane];
+  for (;;) {  // every in-flight batch of the lane may hold an error-word slot
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if ((int64_t)L.inflight.size() < kErrSlots) break;
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
   Batch* b = new Batch;
   b->lane = lane;
   b->reqs = reqs;
-  hipError_t e = hipSuccess;
+  const int64_t seq = ++launch_seq;
+  hipError_t e = seq == inject_launch ? hipErrorLaunchFailure : hipSuccess;
+  bool chunked = false;
   // inputs
   for (Req* r : reqs) {
     const size_t s = esize(r->dt);
@@ -307,8 +335,21 @@ void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
         e = hipErrorOutOfMemory;
       else
         e = mm::launch_1d(g.dt, mm::kStratChunk, a, (int)std::min<int64_t>(ac, mm::grid_cap(g.dt, mm::kStratChunk)), L.st);
+      chunked = true;
     }
     pos += gbytes;
+  }
+  // the chunk kernel flags a look-back wait that gave up in the lane's
+  // control words: copy that word out with the batch, then clear it
+  if (e == hipSuccess && seq == inject_err) {
+    e = hipMemsetAsync(&L.ctl->err, 1, sizeof(uint32_t), L.st);
+    chunked = true;
+  }
+  if (e == hipSuccess && chunked) {
+    b->slot = L.next_slot++ % kErrSlots;
+    L.h_err[b->slot] = 0;
+    e = hipMemcpyAsync(&L.h_err[b->slot], &L.ctl->err, sizeof(uint32_t), hipMemcpyDeviceToHost, L.st);
+    if (e == hipSuccess) e = hipMemsetAsync(&L.ctl->err, 0, sizeof(uint32_t), L.st);
   }
   // pushes that complete no window only roll their carry forward
   for (Req* r : reqs) {
@@ -337,9 +378,20 @@ void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
   if (e == hipSuccess) e = hipEventRecord(b->ev, L.st);
   std::lock_guard<std::mutex> lk(mu);
   if (e != hipSuccess) {
-    // nothing usable was produced: fail the batch's requests right away
+    // nothing usable was produced: fail the batch's requests right away and
+    // return each pushed stream to its state before the push (admission
+    // advanced it; no later push of the stream has been admitted yet, since
+    // admission and launch alternate on this thread), so the caller may
+    // push the chunk again
     hipStreamSynchronize(L.st);
     for (Req* r : reqs) {
+      if (r->kind == kPush) {
+        auto it = streams.find(r->sid);
+        if (it != streams.end()) {
+          it->second.cur = 1 - it->second.cur;
+          it->second.t -= r->n;
+        }
+      }
       arena.release(r->off, r->bytes);
       finish(r, MAXMIN_EDEVICE);
     }
@@ -404,10 +456,18 @@ void maxmin_engine::poller_loop() {
       while (!L.inflight.empty()) {
         Batch* b = L.inflight.front();
         if (hipEventQuery(b->ev) != hipSuccess) break;
+        // a look-back wait that gave up leaves every output of the batch
+        // suspect, and the carries its pushes wrote: fail them all and
+        // mark those streams broken
+        const bool bad = b->slot >= 0 && L.h_err[b->slot] != 0;
         for (Req* r : b->reqs) {
           arena.release(r->off, r->bytes);
-          elems_done += r->n;
-          finish(r, MAXMIN_OK);
+          if (bad && r->kind == kPush) {
+            auto it = streams.find(r->sid);
+            if (it != streams.end()) it->second.broken = true;
+          }
+          if (!bad) elems_done += r->n;
+          finish(r, bad ? MAXMIN_EDEVICE : MAXMIN_OK);
         }
         hipEventDestroy(b->ev);
         L.inflight.pop_front();
@@ -431,6 +491,11 @@ int maxmin_engine_create(int64_t hbm_budget_bytes, int n_lanes, int64_t max_batc
     return mm::set_error(MAXMIN_EINVAL, "maxmin_engine_create: budget >= 1 MiB, 1..16 lanes, max_batch >= 1");
   std::unique_ptr<maxmin_engine> e(new maxmin_engine);
   hipGetDevice(&e->device);
+  if (const char* inj = getenv("MAXMIN_ENGINE_INJECT")) {
+    long long k = 0;
+    if (sscanf(inj, "launch:%lld", &k) == 1) e->inject_launch = k;
+    if (sscanf(inj, "err:%lld", &k) == 1) e->inject_err = k;
+  }
   if (hipMalloc((void**)&e->arena.base, (size_t)hbm_budget_bytes) != hipSuccess)
     return mm::set_error(MAXMIN_ENOMEM, "maxmin_engine_create: cannot allocate the HBM budget");
   e->arena.size = hbm_budget_bytes & ~int64_t(255);
@@ -449,11 +514,12 @@ int maxmin_engine_create(int64_t hbm_budget_bytes, int n_lanes, int64_t max_batc
     L.desc_cap = (size_t)max_batch * mm::series_bytes() + 2 * ((size_t)max_batch + 8) * sizeof(int64_t);
     uint64_t* ring;
     uint32_t lg;
-    mm::Ctl* ctl;
     if (hipMalloc((void**)&L.desc, L.desc_cap) != hipSuccess ||
-        mm::stream_lookback_state(L.st, int64_t(1) << 20, &ring, &lg, &ctl) != MAXMIN_OK) {
+        hipHostMalloc((void**)&L.h_err, kErrSlots * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+        mm::stream_lookback_state(L.st, int64_t(1) << 20, &ring, &lg, &L.ctl) != MAXMIN_OK) {
       for (auto& M : e->lanes) {
         if (M.desc) hipFree(M.desc);
+        if (M.h_err) hipHostFree(M.h_err);
         hipStreamDestroy(M.st);
       }
       hipFree(e->arena.base);
@@ -611,6 +677,7 @@ int maxmin_engine_destroy(maxmin_engine_t* eng) {
   for (auto& L : eng->lanes) {
     hipStreamDestroy(L.st);
     hipFree(L.desc);
+    hipHostFree(L.h_err);
   }
   hipFree(eng->arena.base);
   delete eng;

@@ -147,6 +147,9 @@ enum Strategy : int {
 int grid_cap(int dtype, int strategy);
 
 hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStream_t st);
+// One series (a.mode 0, w <= kTileMaxW4) with the tile kernel: run length
+// and grid as the planner sets them (mm_abi.cpp); no scratch memory.
+hipError_t launch_tile_series(int dtype, JobArgs a, hipStream_t st);
 // Single series (a.mode 0) with more than one chunk per block of w: chunk
 // aggregates into agg (2 * chunk_count(n, w, long_chunk_max(w)) elements),
 // then one column of chunks per workgroup (no look-back, no re-read of the

@@ -149,3 +149,55 @@ def test_engine_replay_open_loop():
             assert_bits_equal(outs[i][1].numpy()[:no], emn, "replay min")
     eng.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["launch", "err"])
+def test_engine_failed_batch(mode, monkeypatch):
+    """A failed batch finishes its requests with EDEVICE, forced from the
+    host (MAXMIN_ENGINE_INJECT: the second batch fails before anything is
+    enqueued, or its look-back error word reads as set; every kernel runs
+    normally).  After a failed launch the pushed stream is as it was before
+    the push: pushing the same chunk again continues the series exactly.
+    After a device error the stream is broken (later pushes fail) while
+    other requests still complete."""
+    import torch
+    rng = synth.rng_for("tests", 430)
+    monkeypatch.setenv("MAXMIN_ENGINE_INJECT", "%s:2" % mode)
+    eng = mm.MaxMinEngine(budget_bytes=256 << 20, lanes=1, max_batch=8)
+    monkeypatch.delenv("MAXMIN_ENGINE_INJECT")
+    w, m = 512, 4096
+    series = synth.random_walk(3 * m, np.float32, rng)
+    sid = eng.open_stream(torch.float32, w)
+
+    def push(p):
+        hc = _pin(series[p * m:(p + 1) * m])
+        mx, mn = _empty(m, np.float32), _empty(m, np.float32)
+        rid = eng.submit_push(sid, hc, mx, mn)
+        eng.drain()
+        _, no, _, status = {r[0]: r for r in eng.poll()}[rid]
+        return status, mx.numpy()[:no].copy(), mn.numpy()[:no].copy()
+
+    note("engine injected %s failure" % mode)
+    s1, mx1, mn1 = push(0)
+    s2, _, _ = push(1)
+    assert s1 == mm.MAXMIN_OK and s2 == mm.MAXMIN_EDEVICE
+    if mode == "launch":
+        s2b, mx2, mn2 = push(1)
+        s3, mx3, mn3 = push(2)
+        assert s2b == mm.MAXMIN_OK and s3 == mm.MAXMIN_OK
+        emx, emn = oracle.wedge(series, w)
+        assert_bits_equal(np.concatenate([mx1, mx2, mx3]), emx, "stream max after a failed launch")
+        assert_bits_equal(np.concatenate([mn1, mn2, mn3]), emn, "stream min after a failed launch")
+    else:
+        assert push(2)[0] == mm.MAXMIN_EDEVICE  # broken
+        a = synth.random_walk(20000, np.float32, rng)
+        mx, mn = _empty(a.size, np.float32), _empty(a.size, np.float32)
+        rid = eng.submit_filter(_pin(a), 300, mx, mn)
+        eng.drain()
+        _, no, _, status = {r[0]: r for r in eng.poll()}[rid]
+        assert status == mm.MAXMIN_OK
+        emx, emn = oracle.wedge(a, 300)
+        assert_bits_equal(mx.numpy()[:no], emx, "filter after a device error max")
+        assert_bits_equal(mn.numpy()[:no], emn, "filter after a device error min")
+    eng.close_stream(sid)
+    eng.close()
