@@ -75,6 +75,27 @@ int maxmin_filter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max
                   void* d_min, void* stream);
 
 /*
+ * maxmin_filter_noalloc -- maxmin_filter that allocates nothing, for callers
+ * that cannot call hipMalloc: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same arguments, outputs and
+ * bits as maxmin_filter; the caller passes the inputs and outputs as usual.
+ *   Scratch: windows w <= 8192 need none.  Longer windows keep their chunk
+ *   aggregates (2 * chunks * element size bytes, chunks <= n / 1024 + 1) in
+ *   a fixed 32 MiB device array inside the library, which every GPU the
+ *   library runs on holds until the process ends; a call that would need
+ *   more (e.g. more than 2^31 elements of 8-byte data) returns
+ *   MAXMIN_EUNSUPPORTED before enqueuing anything.  Nothing in the array
+ *   needs clearing (the first pass writes every aggregate the second reads).
+ *   Calls with w > 8192 that overlap on one GPU (different streams, or
+ *   different host threads) share that array and race: serialise them.
+ *   Forced strategies (maxmin_set_strategy) are ignored: w <= 8192 takes the
+ *   tile kernel, longer windows the two-pass chunk kernels.
+ * Errors: as maxmin_filter, plus EUNSUPPORTED (scratch too small).
+ */
+int maxmin_filter_noalloc(int dtype, const void* d_in, int64_t n, int64_t w, void* d_max,
+                          void* d_min, void* stream);
+
+/*
  * maxmin_argfilter -- one series: the window max and min (as maxmin_filter)
  * and their locations (Section 5: an implementation that stores locations
  * gives the arg max/min filter at no extra cost).  Ties: the LEFTMOST

@@ -41,6 +41,7 @@ def lib():
         i64, vp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.maxmin_filter.argtypes = [ci, vp, i64, i64, vp, vp, vp]
+        L.maxmin_filter_noalloc.argtypes = [ci, vp, i64, i64, vp, vp, vp]
         L.maxmin_argfilter.argtypes = [ci, vp, i64, i64, vp, vp, vp, vp, vp]
         L.maxmin_filter_batched.argtypes = [ci, vp, vp, vp, vp, i64, vp, vp, vp]
         L.maxmin_out_offsets.argtypes = [vp, vp, i64, vp]
@@ -78,7 +79,7 @@ def lib():
             getattr(L, f).restype = ci
         L.maxmin_last_error.restype = ctypes.c_char_p
         L.maxmin_version.restype = ctypes.c_char_p
-        for f in ("maxmin_filter", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
+        for f in ("maxmin_filter", "maxmin_filter_noalloc", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
                   "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_morph_2d",
                   "maxmin_envelope", "maxmin_envelope_batched", "maxmin_autotune", "maxmin_tuning",
                   "maxmin_set_strategy",
@@ -154,6 +155,15 @@ def maxmin_filter(x, w, out_max=None, out_min=None, stream=None, which="both"):
     out_max, out_min = (out_max if wx else None), (out_min if wn else None)
     _check(lib().maxmin_filter(dtype_code(x.dtype), _ptr(x), x.numel(), int(w), _ptr(out_max), _ptr(out_min),
                                _stream(stream)))
+    return out_max, out_min
+
+
+def maxmin_filter_noalloc(x, w, out_max, out_min, stream=None):
+    """maxmin_filter into caller-given outputs with no allocation by the
+    library (its long-window scratch is a fixed device array)."""
+    _cuda_1d(x, "x")
+    _check(lib().maxmin_filter_noalloc(dtype_code(x.dtype), _ptr(x), x.numel(), int(w), _ptr(out_max),
+                                       _ptr(out_min), _stream(stream)))
     return out_max, out_min
 
 

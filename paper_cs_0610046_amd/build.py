@@ -18,7 +18,7 @@ LIB_NAME = "libmaxmin.so"
 LIB_PATH = os.path.join(OUT_DIR, LIB_NAME)
 
 SOURCES = ["mm_kernels_1d.hip", "mm_kernels_2d.hip", "mm_kernels_2d_max.hip", "mm_kernels_2d_min.hip",
-           "mm_kernels_env.hip", "mm_kernels_arg.hip", "mm_abi.cpp", "mm_engine.cpp"]
+           "mm_kernels_env.hip", "mm_kernels_arg.hip", "mm_abi.cpp", "mm_engine.cpp", "mm_noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

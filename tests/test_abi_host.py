@@ -65,6 +65,14 @@ def test_argument_errors_without_gpu(lib):
         binding.MAXMIN_EINVAL
     assert lib.maxmin_argfilter(0, vp(0x1000), 10, 3, vp(0x2000), vp(0x3000), vp(0x4004), vp(0x5000), None) == \
         binding.MAXMIN_EINVAL  # location output not 8-byte aligned
+    # no-allocation entry point: argument checks, and a long window whose
+    # aggregates exceed its fixed scratch is refused before any device call
+    assert lib.maxmin_filter_noalloc(0, None, 10, 0, None, None, None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_filter_noalloc(0, None, 10, 11, None, None, None) == binding.MAXMIN_OK
+    assert lib.maxmin_filter_noalloc(0, vp(0x1002), 10, 3, vp(0x2000), vp(0x3000), None) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_filter_noalloc(1, vp(0x1000), 1 << 34, 10000, vp(0x2000), vp(0x3000), None) == \
+        binding.MAXMIN_EUNSUPPORTED
+    assert "32 MiB" in binding.maxmin_last_error()
     assert lib.maxmin_set_strategy(9) == binding.MAXMIN_EINVAL
     assert lib.maxmin_set_strategy(3) == binding.MAXMIN_OK
     assert lib.maxmin_set_strategy(0) == binding.MAXMIN_OK
