@@ -190,7 +190,7 @@ def main():
     tuning = mm.maxmin_tuning(torch.float32)
     if args.autotune:
         t0 = time.time()
-        tuning = mm.maxmin_autotune(torch.float32, 1 << 26)
+        tuning = mm.maxmin_autotune(torch.float32, 1 << 28)
         print("[bench] autotune %.2fs: %s" % (time.time() - t0, tuning), file=sys.stderr, flush=True)
     n = 1 << args.n_log2
     t0 = time.time()

@@ -210,26 +210,43 @@ int maxmin_envelope_batched(int dtype, const void* d_in, const int64_t* d_in_off
 
 /*
  * maxmin_autotune -- measure the planner's launch parameters for `dtype` on
- * the current device and keep the fastest, process-wide: the tile run length
- * (sub-tiles per run), the ticket-range count of one-chunk windows, the
- * strategy (chunk or chunk runs) and range count of longer windows, and the
- * run length of the 2-D filter's row pass.  Allocates and frees 3 n elements
- * of device memory (n = 0: 2^26), leaves the stream's 2-D scratch images
- * (up to 2 n elements) in place for later calls, and synchronises `stream`;
- * results of every call stay bit-identical whatever it picks.  Not during
- * graph capture (EBUSY).  Calls made concurrently on other threads may see
- * the table change midway (each launch reads it once).
+ * the current device and keep the fastest, process-wide (a value changes
+ * only when more than 3% faster): the tile kernel's run length for w <=
+ * 2048 and for 2048 < w <= 8192, the ticket-range counts of the look-back
+ * chunk kernel, the strategy for w > 8192 (chunk or chunk runs), the run
+ * length of the 2-D row pass, and the batched plan: for every size class
+ * with windows up to 8192 -- window class (<= 2048, <= 4096, <= 8192) by
+ * length class (n < 2^16, < 2^20, longer) -- the tile or the chunk kernel,
+ * each measured on a batch of that class, then the batched tile size (1, 2
+ * or 4 sub-tiles of 2048 windows) on a batch shaped like 10,000 series of
+ * lengths log-uniform in [1e3, 1e6] with windows in [2, 1024] (fewer series
+ * if device memory is short).  Single-series knobs are measured on a
+ * pseudo-random series of n elements (n = 0: 2^28).  Allocates and frees
+ * its buffers (about 3 n elements plus the batches), leaves the stream's
+ * 2-D scratch images in place, and synchronises `stream`; results of every
+ * call stay bit-identical whatever it picks.  Not during graph capture
+ * (EBUSY).  Calls made concurrently on other threads may see the table
+ * change midway (each launch reads it once).
  * Errors: EINVAL for an unknown dtype or 0 < n < 2^20; ENOMEM.
  */
 int maxmin_autotune(int dtype, int64_t n, void* stream);
 
 /*
- * maxmin_tuning -- the current table for `dtype`: out6 = {tile run
- * (sub-tiles), 2-D row-pass run (sub-tiles), ranges for one-chunk windows, ranges
- * for longer windows, strategy for w > 8192 (MAXMIN_STRATEGY_CHUNK or _RUN),
- * 1 if measured by maxmin_autotune else 0}.  Host only.
+ * maxmin_tuning -- the current table for `dtype`, MAXMIN_TUNING_LEN entries:
+ *   [0] tile run, w <= 2048 (sub-tiles)   [1] tile run, 2048 < w <= 8192
+ *   [2] 2-D row-pass run (sub-tiles)      [3] ticket ranges, one-chunk windows
+ *   [4] ticket ranges, look-back kernel   [5] strategy for w > 8192
+ *                                             (MAXMIN_STRATEGY_CHUNK or _RUN)
+ *   [6] batched tile (sub-tiles)
+ *   [7 + 3 wc + nc] batched strategy of size class (wc, nc): 0 tile kernel,
+ *       1 chunk kernel; wc = 0, 1, 2 for w <= 2048, <= 4096, <= 8192;
+ *       nc = 0, 1, 2 for n < 2^16, < 2^20, longer (longer windows always
+ *       take the chunk kernel)
+ *   [16] 1 if measured by maxmin_autotune, else 0 (the built-in defaults).
+ * Host only.
  */
-int maxmin_tuning(int dtype, int64_t* out6);
+#define MAXMIN_TUNING_LEN 17
+int maxmin_tuning(int dtype, int64_t* out);
 
 /* Grey-scale morphology operators of maxmin_morph_2d. */
 typedef enum {

@@ -319,13 +319,25 @@ def maxmin_autotune(dtype, n=0, stream=None):
     return maxmin_tuning(dtype)
 
 
+TUNING_LEN = 17
+BATCH_WCLASSES = ("w<=2048", "w<=4096", "w<=8192")
+BATCH_NCLASSES = ("n<2^16", "n<2^20", "n>=2^20")
+
+
 def maxmin_tuning(dtype):
-    """The planner's launch parameters for ``dtype`` (host only)."""
-    out = (ctypes.c_int64 * 6)()
+    """The planner's launch parameters for ``dtype`` (host only): run
+    lengths, ticket ranges, the long-window strategy and the batched plan
+    (tile size and, per size class, "tile" or "chunk")."""
+    out = (ctypes.c_int64 * TUNING_LEN)()
     _check(lib().maxmin_tuning(dtype_code(dtype), out))
-    return {"tile_run_subtiles": out[0], "rows_run_subtiles": out[1], "chunk_ranges_one_chunk": out[2],
-            "chunk_ranges_long": out[3], "long_window_strategy": {2: "chunk", 3: "run"}.get(out[4], out[4]),
-            "measured": bool(out[5])}
+    plan = {}
+    for wc, wn in enumerate(BATCH_WCLASSES):
+        for nc, nn in enumerate(BATCH_NCLASSES):
+            plan["%s,%s" % (wn, nn)] = "tile" if out[7 + 3 * wc + nc] == 0 else "chunk"
+    return {"tile_run_subtiles": out[0], "tile_run_subtiles_long": out[1], "rows_run_subtiles": out[2],
+            "chunk_ranges_one_chunk": out[3], "chunk_ranges_long": out[4],
+            "long_window_strategy": {2: "chunk", 3: "run"}.get(out[5], out[5]),
+            "batched_tile_subtiles": out[6], "batched_plan": plan, "measured": bool(out[16])}
 
 
 MORPH_OPS = {"erode": 0, "dilate": 1, "open": 2, "close": 3}

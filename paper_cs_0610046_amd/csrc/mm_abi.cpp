@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -63,19 +64,51 @@ std::atomic<int> g_force{0};
 // Launch parameters the planner uses, per dtype.  The defaults are the
 // choices measured best on MI355X; maxmin_autotune re-measures them on the
 // device at hand.  Environment variables still override (experiments).
+// On MI355X (n = 2^28 float32) runs of 4 sub-tiles for w <= 2048 ran 4-5%
+// faster than 16 (w = 16: 0.612 against 0.642 ms, w = 256: 0.648 against
+// 0.674 ms); longer windows re-read up to four sub-tiles of halo per run
+// and keep runs of 64 (16 sub-tiles there: 0.72 against 0.69 ms at 4096).
+mm::BatchPlan default_plan() {
+  mm::BatchPlan p{};
+  for (int wc = 0; wc < mm::kBatchWClasses; ++wc)
+    for (int nc = 0; nc < mm::kBatchNClasses; ++nc) p.strat[wc][nc] = wc < 3 ? mm::kBatchTile : mm::kBatchChunk;
+  p.run_subtiles = 1;
+  return p;
+}
 struct Tuning {
-  int tile_run = 16;     // sub-tiles per run, single-series tile launches
-  int batched_run = 16;  // sub-tiles per run, row pass of the 2-D filter
-  int ranges_one = 16;   // chunk ticket ranges, one-chunk windows (w <= 4096; chunk strategy forced)
-  int ranges_long = 0;   // chunk ticket ranges, longer windows
+  int tile_run = 4;        // sub-tiles per run, single-series tile launches, w <= 2048
+  int tile_run_long = 64;  // the same for 2048 < w <= 8192
+  int rows_run = 16;       // sub-tiles per run, row pass of the 2-D filter
+  int ranges_one = 16;     // chunk ticket ranges, one-chunk windows (w <= 4096; chunk strategy forced)
+  int ranges_long = 0;     // chunk ticket ranges, longer windows on the look-back kernel
   int long_strategy = MAXMIN_STRATEGY_CHUNK;  // w > 8192: chunk or run
+  mm::BatchPlan batch = default_plan();       // batched calls: strategy per size class, tile size
   int tuned = 0;
 };
 std::mutex g_tune_mu;
 Tuning g_tune[4];
+std::atomic<int64_t> g_tune_version{0};  // bumped on every change (keys the batched graph cache)
 Tuning tuning(int dt) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   return g_tune[dt >= 0 && dt < 4 ? dt : 0];
+}
+
+// The batched plan of `dt`, with the experiment overrides MAXMIN_BATCH_PLAN
+// (tile / chunk: that strategy for every class it applies to) and
+// MAXMIN_BATCH_RUN (tile size in sub-tiles).
+mm::BatchPlan batch_plan(int dt) {
+  mm::BatchPlan p = tuning(dt).batch;
+  if (const char* e = getenv("MAXMIN_BATCH_PLAN")) {
+    const int f = !strcmp(e, "chunk") ? mm::kBatchChunk : (!strcmp(e, "tile") ? mm::kBatchTile : -1);
+    if (f >= 0)
+      for (int wc = 0; wc < 3; ++wc)
+        for (int nc = 0; nc < mm::kBatchNClasses; ++nc) p.strat[wc][nc] = (uint8_t)f;
+  }
+  if (const char* e = getenv("MAXMIN_BATCH_RUN")) {
+    const int r = atoi(e);
+    if (r >= 1 && r <= 64) p.run_subtiles = r;
+  }
+  return p;
 }
 
 int env_strategy() {
@@ -162,7 +195,7 @@ int tile_kind(int64_t w) {
 }
 
 // ------------------------------------------------------------ workspaces
-typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*, int64_t> GraphKey;
+typedef std::tuple<int, const void*, const void*, const void*, const void*, int64_t, void*, void*, std::string> GraphKey;
 
 struct Workspace {
   int device = 0;
@@ -270,7 +303,7 @@ int ensure_ring(Workspace* ws, int64_t ntiles) {
 }
 
 int ensure_batch(Workspace* ws, int64_t S) {
-  if (ws->descs && ws->desc_cap >= S && ws->pre_cap >= S + 1) return MAXMIN_OK;
+  if (ws->descs && ws->desc_cap >= S && ws->pre_cap >= mm::batch_pre_len(S)) return MAXMIN_OK;
   int r = grow_guard(ws, "batched descriptors");
   if (r) return r;
   if (ws->descs) hipFree(ws->descs);
@@ -279,12 +312,11 @@ int ensure_batch(Workspace* ws, int64_t S) {
   ws->pre = nullptr;
   const int64_t cap = std::max<int64_t>(S, 1024);
   hipError_t e = hipMalloc(&ws->descs, (size_t)cap * mm::series_bytes());
-  // two prefix arrays of cap + 1, then the setup's per-workgroup totals
-  if (e == hipSuccess)
-    e = hipMalloc((void**)&ws->pre, (size_t)(2 * (cap + 1) + 2 * mm::kBatchMaxGroups + 2) * sizeof(int64_t));
+  // one prefix array of cap + 1 per path, then the setup's per-workgroup totals
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->pre, (size_t)mm::batch_pre_len(cap) * sizeof(int64_t));
   if (e != hipSuccess) return fail(MAXMIN_ENOMEM, "hipMalloc(batched descriptors): %s", hipGetErrorString(e));
   ws->desc_cap = cap;
-  ws->pre_cap = cap + 1;
+  ws->pre_cap = mm::batch_pre_len(cap);
   return MAXMIN_OK;
 }
 
@@ -328,7 +360,8 @@ hipError_t launch_tile_series(int dt, JobArgs a, hipStream_t st) {
   // a run re-reads the w-1 inputs after it: runs 4x longer for windows
   // over more than one sub-tile (MI355X, n = 2^28 float32, w =
   // 2049..4096: 64 sub-tiles 0.71-0.73 ms, 32: 0.72-0.73, 16: 0.74-0.75)
-  const int64_t rmax = (int64_t)tuning(dt).tile_run * (ks == kStratTile ? 1 : 4) * kTileOut;
+  const Tuning t = tuning(dt);
+  const int64_t rmax = (int64_t)(ks == kStratTile ? t.tile_run : t.tile_run_long) * kTileOut;
   a.run = run_length(a.n - a.w + 1, cap, rmax);
   if (const char* e = getenv("MAXMIN_TILE_RUN")) {
     const int64_t r = atoll(e) / kTileOut * kTileOut;
@@ -405,6 +438,7 @@ int stream_lookback_state(hipStream_t stream, int64_t ntiles, uint64_t** ring, u
   return MAXMIN_OK;
 }
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+BatchPlan batch_plan_for(int dtype) { return batch_plan(dtype); }
 }  // namespace mm
 
 struct maxmin_stream {
@@ -607,25 +641,28 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
   if ((r = ensure_batch(ws, S))) return r;
   if ((r = ensure_ring(ws, int64_t(1) << kRingMaxLg))) return r;
 
-  // tiles of one sub-tile: the tile kernel streams each workgroup's
-  // contiguous range of them series by series, so their size only sets
-  // how evenly the ranges split
-  const int64_t brun = mm::kRunBatched;
+  // One launch per path: the tile kernel of each lag (each workgroup
+  // streams a contiguous range of its tiles, series by series, so the tile
+  // size only sets how evenly the ranges split) and the chunk kernel; the
+  // path of every series comes from the plan's strategy for its size class.
+  const mm::BatchPlan plan = batch_plan(dtype);
   auto enqueue = [&]() -> hipError_t {
-    int64_t* pre_tile = ws->pre;
-    int64_t* pre_chunk = ws->pre + (S + 1);
+    int64_t* pre = ws->pre;
     hipError_t e = mm::launch_batched_setup(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min,
-                                            ws->descs, pre_tile, pre_chunk, st, brun);
+                                            ws->descs, pre, plan, st);
     if (e != hipSuccess) return e;
     JobArgs a;
     a.mode = 1;
     a.descs = ws->descs;
     a.S = S;
-    a.pre = pre_tile;
-    a.run = brun;
-    e = mm::launch_1d(dtype, mm::kStratTile, a, mm::grid_cap(dtype, mm::kStratTile), st);
-    if (e != hipSuccess) return e;
-    a.pre = pre_chunk;
+    a.run = (int64_t)plan.run_subtiles * mm::kTileOut;
+    static const int kinds[4] = {mm::kStratTile, mm::kStratTile2, mm::kStratTile3, mm::kStratTile4};
+    for (int p = 0; p < 4; ++p) {
+      a.pre = pre + p * (S + 1);
+      e = mm::launch_1d(dtype, kinds[p], a, mm::grid_cap(dtype, kinds[p]), st);
+      if (e != hipSuccess) return e;
+    }
+    a.pre = pre + mm::kBatchChunkPath * (S + 1);
     a.ring = ws->ring;
     a.ring_lg = ws->ring_lg;
     a.ctl = ws->ctl;
@@ -638,7 +675,8 @@ int maxmin_filter_batched(int dtype, const void* d_in, const int64_t* d_in_offse
     return ok();
   }
   // replay a captured graph of the three launches when the same call repeats
-  GraphKey key(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min, brun);
+  GraphKey key(dtype, d_in, d_in_offsets, d_windows, d_out_offsets, S, d_max, d_min,
+               std::string((const char*)&plan, sizeof plan));
   auto it = ws->graphs.find(key);
   if (it == ws->graphs.end()) {
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -792,7 +830,7 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   const int strat = plan_strategy(dtype, cols, w_cols);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
-    a.run = (int64_t)tuning(dtype).batched_run * mm::kTileOut;
+    a.run = (int64_t)tuning(dtype).rows_run * mm::kTileOut;
     a.tpr = mm::run_count(cols, w_cols, a.run);
     a.ntiles = a.tpr * rows;
     const int ks = tile_kind(w_cols);
@@ -911,38 +949,102 @@ int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int
                           ld_out, stream);
 }
 
-// Autotuner: measure each launch parameter of the planner (Tuning) on this
+// Autotuner: measure the planner's launch parameters (Tuning) on this
 // device for `dtype`, one knob at a time with the others at their best so
-// far, and keep the fastest (a change needs more than 3% to count).  Inputs
-// are a constant-filled series of n elements (selection time does not
-// depend on the values); each candidate is the best of five timed launches
+// far; a candidate replaces the current value only if it is more than 3%
+// faster (run-to-run noise must not move the table).  Inputs are a
+// pseudo-random pattern written on the device (selection time does not
+// depend on the values).  Each candidate is the best of five timed calls
 // after one warm-up.
+//  * one series of n elements (0: 2^28): the run length of the tile kernel
+//    for w <= 2048 (measured at w = 256) and for 2048 < w <= 8192 (4096);
+//    ticket ranges of one-chunk windows (only when the chunk strategy is
+//    forced); the long-window strategy (65536); the look-back kernel's
+//    ticket ranges (16384, a window that takes it);
+//  * the 2-D row pass run length (the series as an image of 8192 columns,
+//    63 x 63 windows);
+//  * batched calls: per size class with windows up to 8192 (window class x
+//    length class), tile or chunk kernel, each measured on a batch of its
+//    class (about 2^25 elements); then the tile size (1, 2 or 4 sub-tiles)
+//    on a batch shaped like the benchmark's: 10,000 series, lengths
+//    log-uniform in [1e3, 1e6], windows uniform in [2, 1024] (fewer series
+//    when device memory is short).
 int maxmin_autotune(int dtype, int64_t n, void* stream) {
   const size_t s = dsize(dtype);
   if (!s) return fail(MAXMIN_EINVAL, "maxmin_autotune: unknown dtype %d", dtype);
-  if (n == 0) n = int64_t(1) << 26;
+  if (n == 0) n = int64_t(1) << 28;
   if (n < (int64_t(1) << 20)) return fail(MAXMIN_EINVAL, "maxmin_autotune: n=%lld < 2^20", (long long)n);
   hipStream_t st = (hipStream_t)stream;
   if (capturing(st)) return fail(MAXMIN_EBUSY, "maxmin_autotune: the stream is being captured");
+  // batches: host descriptions first (sizes decide the buffers)
+  struct HostBatch {
+    std::vector<int64_t> off, win, oo;
+  };
+  uint64_t rs = 0x9E3779B97F4A7C15ull;
+  auto rnd = [&]() {  // xorshift64*, uniform in [0, 1)
+    rs ^= rs >> 12;
+    rs ^= rs << 25;
+    rs ^= rs >> 27;
+    return (double)((rs * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0);
+  };
+  auto make = [&](int64_t S, double nlo, double nhi, int64_t wlo, int64_t whi) {
+    HostBatch b;
+    b.off.assign((size_t)S + 1, 0);
+    b.win.resize((size_t)S);
+    for (int64_t k = 0; k < S; ++k) {
+      const int64_t len = (int64_t)std::floor(std::exp(std::log(nlo) + rnd() * (std::log(nhi) - std::log(nlo))));
+      b.off[k + 1] = b.off[k] + len;
+      b.win[k] = wlo + (int64_t)(rnd() * (double)(whi - wlo + 1));
+      if (b.win[k] > whi) b.win[k] = whi;
+    }
+    b.oo.assign((size_t)S + 1, 0);
+    maxmin_out_offsets(b.off.data(), b.win.data(), S, b.oo.data());
+    return b;
+  };
+  static const double kNLo[3] = {8192.0, 65536.0, 1048576.0}, kNHi[3] = {65535.0, 1048575.0, 4194304.0};
+  static const int64_t kWLo[3] = {2, 2049, 4097}, kWHi[3] = {2048, 4096, 8192};
+  std::vector<HostBatch> cls;
+  for (int wc = 0; wc < 3; ++wc)
+    for (int nc = 0; nc < 3; ++nc) {
+      const double mean = (kNHi[nc] - kNLo[nc]) / std::log(kNHi[nc] / kNLo[nc]);
+      cls.push_back(make(std::max<int64_t>(4, (int64_t)((double)(1 << 25) / mean)), kNLo[nc], kNHi[nc], kWLo[wc],
+                         kWHi[wc]));
+    }
+  size_t fb = 0, tb = 0;
+  hipMemGetInfo(&fb, &tb);
+  int64_t S4 = 10000;
+  while (S4 > 100 && (double)S4 * 144.6e3 * 3.0 * (double)s > 0.4 * (double)fb) S4 /= 2;
+  HostBatch big = make(S4, 1e3, 1e6, 2, 1024);
+  int64_t maxN = n, maxO = n, maxS = S4;
+  for (auto* b : {&big}) {
+    maxN = std::max(maxN, b->off.back());
+    maxO = std::max(maxO, b->oo.back());
+  }
+  for (auto& b : cls) {
+    maxN = std::max(maxN, b.off.back());
+    maxO = std::max(maxO, b.oo.back());
+    maxS = std::max<int64_t>(maxS, (int64_t)b.win.size());
+  }
   void *in = nullptr, *mx = nullptr, *mn = nullptr;
+  int64_t *d_off = nullptr, *d_w = nullptr, *d_oo = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const Tuning before = tuning(dtype);
   int r = MAXMIN_OK;
   auto cleanup = [&]() {
     if (st) hipStreamSynchronize(st);
     else hipDeviceSynchronize();
-    if (in) hipFree(in);
-    if (mx) hipFree(mx);
-    if (mn) hipFree(mn);
+    for (void* q : {in, mx, mn, (void*)d_off, (void*)d_w, (void*)d_oo})
+      if (q) hipFree(q);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
   };
-  if (hipMalloc(&in, (size_t)n * s) != hipSuccess || hipMalloc(&mx, (size_t)n * s) != hipSuccess ||
-      hipMalloc(&mn, (size_t)n * s) != hipSuccess) {
+  if (hipMalloc(&in, (size_t)maxN * s) != hipSuccess || hipMalloc(&mx, (size_t)maxO * s) != hipSuccess ||
+      hipMalloc(&mn, (size_t)maxO * s) != hipSuccess || hipMalloc((void**)&d_off, (maxS + 1) * 8) != hipSuccess ||
+      hipMalloc((void**)&d_w, maxS * 8) != hipSuccess || hipMalloc((void**)&d_oo, (maxS + 1) * 8) != hipSuccess) {
     cleanup();
-    return fail(MAXMIN_ENOMEM, "maxmin_autotune: cannot allocate %lld elements", (long long)n);
+    return fail(MAXMIN_ENOMEM, "maxmin_autotune: cannot allocate its buffers (%lld elements)", (long long)maxN);
   }
-  hipError_t e = hipMemsetAsync(in, 0x3c, (size_t)n * s, st);
+  hipError_t e = mm::launch_tune_fill(dtype, in, maxN, st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) {
@@ -952,6 +1054,7 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
   auto set = [&](const Tuning& t) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[dtype] = t;
+    ++g_tune_version;
   };
   auto time_ms = [&](const std::function<int()>& launch) -> float {
     if ((r = launch())) return 0.f;
@@ -968,17 +1071,17 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
     return best;
   };
   Tuning best = before;
-  // a candidate replaces the current value only if it is more than 3%
-  // faster: run-to-run noise must not move the table
-  auto pick = [&](int Tuning::*field, std::initializer_list<int> cands, const std::function<int()>& launch) {
-    const int cur = best.*field;
+  // try each candidate value of one knob (get / put read and write it)
+  auto pick_knob = [&](const std::function<int(const Tuning&)>& get, const std::function<void(Tuning&, int)>& put,
+                       std::initializer_list<int> cands, const std::function<int()>& launch) {
+    const int cur = get(best);
     float bt = time_ms(launch);
     if (r) return;
     int bv = cur;
     for (int v : cands) {
       if (v == cur) continue;
       Tuning t = best;
-      t.*field = v;
+      put(t, v);
       set(t);
       const float ms = time_ms(launch);
       if (r) return;
@@ -987,25 +1090,54 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
         bv = v;
       }
     }
-    best.*field = bv;
+    put(best, bv);
     set(best);
+  };
+  auto pick = [&](int Tuning::*field, std::initializer_list<int> cands, const std::function<int()>& launch) {
+    pick_knob([field](const Tuning& t) { return t.*field; }, [field](Tuning& t, int v) { t.*field = v; }, cands,
+              launch);
   };
   auto filt = [&](int64_t w) {
     return std::function<int()>([=]() { return maxmin_filter(dtype, in, n, w, mx, mn, stream); });
   };
-  pick(&Tuning::tile_run, {8, 16, 32, 64}, filt(256));
+  pick(&Tuning::tile_run, {2, 4, 8, 16, 32}, filt(256));
+  if (!r) pick(&Tuning::tile_run_long, {16, 32, 64, 128}, filt(4096));
   // one-chunk windows run the tile kernel unless the chunk strategy is
   // forced: only then are their ticket ranges worth measuring
   if (!r && plan_strategy(dtype, n, 4096) == MAXMIN_STRATEGY_CHUNK)
     pick(&Tuning::ranges_one, {0, 8, 16, 32}, filt(4096));
   if (!r && n >= 4 * 65536) pick(&Tuning::long_strategy, {MAXMIN_STRATEGY_CHUNK, MAXMIN_STRATEGY_RUN}, filt(65536));
-  if (!r && n >= 4 * 65536 && best.long_strategy == MAXMIN_STRATEGY_CHUNK)
-    pick(&Tuning::ranges_long, {0, 16}, filt(65536));
+  if (!r && n >= 4 * 16384 && best.long_strategy == MAXMIN_STRATEGY_CHUNK && long_lookback(16384))
+    pick(&Tuning::ranges_long, {0, 16}, filt(16384));
   if (!r)  // the series as an image of 8192 columns, 63 x 63 windows (rows then columns)
-    pick(&Tuning::batched_run, {8, 16, 32}, std::function<int()>([=]() {
+    pick(&Tuning::rows_run, {8, 16, 32}, std::function<int()>([=]() {
            const int64_t cols = 8192, rows = n / cols;
            return maxmin_filter_2d(dtype, in, rows, cols, cols, 63, 63, mx, mn, cols - 62, stream);
          }));
+  // batched: a batch's descriptors go to the device, then its call is timed
+  auto upload = [&](const HostBatch& b) -> std::function<int()> {
+    const int64_t S = (int64_t)b.win.size();
+    hipError_t ee = hipMemcpyAsync(d_off, b.off.data(), (S + 1) * 8, hipMemcpyHostToDevice, st);
+    if (ee == hipSuccess) ee = hipMemcpyAsync(d_w, b.win.data(), S * 8, hipMemcpyHostToDevice, st);
+    if (ee == hipSuccess) ee = hipMemcpyAsync(d_oo, b.oo.data(), (S + 1) * 8, hipMemcpyHostToDevice, st);
+    if (ee == hipSuccess) ee = st ? hipStreamSynchronize(st) : hipDeviceSynchronize();
+    if (ee != hipSuccess) r = hip_fail(ee, "maxmin_autotune (batch descriptors)");
+    return [=]() { return maxmin_filter_batched(dtype, in, d_off, d_w, d_oo, S, mx, mn, stream); };
+  };
+  for (int wc = 0; wc < 3 && !r; ++wc)
+    for (int nc = 0; nc < 3 && !r; ++nc) {
+      auto launch = upload(cls[wc * 3 + nc]);
+      if (r) break;
+      pick_knob([wc, nc](const Tuning& t) { return (int)t.batch.strat[wc][nc]; },
+                [wc, nc](Tuning& t, int v) { t.batch.strat[wc][nc] = (uint8_t)v; }, {mm::kBatchTile, mm::kBatchChunk},
+                launch);
+    }
+  if (!r) {
+    auto launch = upload(big);
+    if (!r)
+      pick_knob([](const Tuning& t) { return (int)t.batch.run_subtiles; },
+                [](Tuning& t, int v) { t.batch.run_subtiles = v; }, {1, 2, 4}, launch);
+  }
   const int rr = r;
   cleanup();
   if (rr) {
@@ -1022,16 +1154,21 @@ int maxmin_autotune(int dtype, int64_t n, void* stream) {
   return ok();
 }
 
-int maxmin_tuning(int dtype, int64_t* out6) {
+// The current table for `dtype` (MAXMIN_TUNING_LEN entries).
+int maxmin_tuning(int dtype, int64_t* out) {
   if (!dsize(dtype)) return fail(MAXMIN_EINVAL, "maxmin_tuning: unknown dtype %d", dtype);
-  if (!out6) return fail(MAXMIN_EINVAL, "maxmin_tuning: null pointer");
+  if (!out) return fail(MAXMIN_EINVAL, "maxmin_tuning: null pointer");
   const Tuning t = tuning(dtype);
-  out6[0] = t.tile_run;
-  out6[1] = t.batched_run;
-  out6[2] = t.ranges_one;
-  out6[3] = t.ranges_long;
-  out6[4] = t.long_strategy;
-  out6[5] = t.tuned;
+  out[0] = t.tile_run;
+  out[1] = t.tile_run_long;
+  out[2] = t.rows_run;
+  out[3] = t.ranges_one;
+  out[4] = t.ranges_long;
+  out[5] = t.long_strategy;
+  out[6] = t.batch.run_subtiles;
+  for (int wc = 0; wc < 3; ++wc)
+    for (int nc = 0; nc < 3; ++nc) out[7 + wc * 3 + nc] = t.batch.strat[wc][nc];
+  out[16] = t.tuned;
   return ok();
 }
 

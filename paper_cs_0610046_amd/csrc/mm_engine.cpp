@@ -295,47 +295,52 @@ void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
     }
     g->reqs.push_back(r);
   }
+  // per dtype: descriptors, then one tile-prefix array per path (tile kernel
+  // of lag 1..4, chunk kernel; the path from the batched plan's size
+  // classes), built here on the host; one launch per path present
+  constexpr int NP = mm::kBatchNP;
   size_t total = 0;
-  for (auto& g : groups) total += g.reqs.size() * mm::series_bytes() + 2 * (g.reqs.size() + 1) * sizeof(int64_t);
+  for (auto& g : groups) total += g.reqs.size() * mm::series_bytes() + NP * (g.reqs.size() + 1) * sizeof(int64_t);
   if (total > L.desc_cap) e = hipErrorOutOfMemory;  // cannot happen: admission caps the batch size
   b->host.resize(total);
   size_t pos = 0;
+  static const int kinds[NP] = {mm::kStratTile, mm::kStratTile2, mm::kStratTile3, mm::kStratTile4, mm::kStratChunk};
   for (auto& g : groups) {
     if (e != hipSuccess) break;
     const int64_t S = (int64_t)g.reqs.size();
+    const mm::BatchPlan plan = mm::batch_plan_for(g.dt);
+    const int64_t run = (int64_t)plan.run_subtiles * mm::kTileOut;
     char* hd = b->host.data() + pos;
     char* dd = L.desc + pos;
-    int64_t* pre_tile = (int64_t*)(hd + S * mm::series_bytes());
-    int64_t* pre_chunk = pre_tile + (S + 1);
-    int64_t at = 0, ac = 0;
+    int64_t* pre = (int64_t*)(hd + S * mm::series_bytes());
+    int64_t acc[NP] = {0, 0, 0, 0, 0};
     for (int64_t k = 0; k < S; ++k) {
       Req* r = g.reqs[k];
       std::memcpy(hd + k * mm::series_bytes(), &r->ser, mm::series_bytes());
-      pre_tile[k] = at;
-      pre_chunk[k] = ac;
-      if (r->ser.w <= mm::kTileMaxW) at += mm::run_count(r->ser.n, r->ser.w, mm::kRunBatched);
-      else ac += mm::chunk_count(r->ser.n, r->ser.w);
+      for (int q = 0; q < NP; ++q) pre[q * (S + 1) + k] = acc[q];
+      const int path = mm::batch_path(plan, r->ser.n, r->ser.w);
+      if (path >= 0) acc[path] += mm::batch_tiles(path, r->ser.n, r->ser.w, run);
     }
-    pre_tile[S] = at;
-    pre_chunk[S] = ac;
-    const size_t gbytes = S * mm::series_bytes() + 2 * (S + 1) * sizeof(int64_t);
+    for (int q = 0; q < NP; ++q) pre[q * (S + 1) + S] = acc[q];
+    const size_t gbytes = S * mm::series_bytes() + NP * (S + 1) * sizeof(int64_t);
     e = hipMemcpyAsync(dd, hd, gbytes, hipMemcpyHostToDevice, L.st);
     mm::JobArgs a;
     a.mode = 1;
     a.descs = dd;
     a.S = S;
-    if (e == hipSuccess && at > 0) {
-      a.pre = (const int64_t*)(dd + S * mm::series_bytes());
-      a.run = mm::kRunBatched;
-      e = mm::launch_1d(g.dt, mm::kStratTile, a, (int)std::min<int64_t>(at, mm::grid_cap(g.dt, mm::kStratTile)), L.st);
-    }
-    if (e == hipSuccess && ac > 0) {
-      a.pre = (const int64_t*)(dd + S * mm::series_bytes()) + (S + 1);
-      if (mm::stream_lookback_state(L.st, std::min<int64_t>(ac, int64_t(1) << 20), &a.ring, &a.ring_lg, &a.ctl) != MAXMIN_OK)
-        e = hipErrorOutOfMemory;
-      else
-        e = mm::launch_1d(g.dt, mm::kStratChunk, a, (int)std::min<int64_t>(ac, mm::grid_cap(g.dt, mm::kStratChunk)), L.st);
-      chunked = true;
+    a.run = run;
+    for (int q = 0; q < NP && e == hipSuccess; ++q) {
+      if (acc[q] == 0) continue;
+      a.pre = (const int64_t*)(dd + S * mm::series_bytes()) + q * (S + 1);
+      if (kinds[q] == mm::kStratChunk) {
+        if (mm::stream_lookback_state(L.st, std::min<int64_t>(acc[q], int64_t(1) << 20), &a.ring, &a.ring_lg,
+                                      &a.ctl) != MAXMIN_OK) {
+          e = hipErrorOutOfMemory;
+          break;
+        }
+        chunked = true;
+      }
+      e = mm::launch_1d(g.dt, kinds[q], a, (int)std::min<int64_t>(acc[q], mm::grid_cap(g.dt, kinds[q])), L.st);
     }
     pos += gbytes;
   }
@@ -511,7 +516,7 @@ int maxmin_engine_create(int64_t hbm_budget_bytes, int n_lanes, int64_t max_batc
     }
   }
   for (auto& L : e->lanes) {
-    L.desc_cap = (size_t)max_batch * mm::series_bytes() + 2 * ((size_t)max_batch + 8) * sizeof(int64_t);
+    L.desc_cap = (size_t)max_batch * mm::series_bytes() + mm::kBatchNP * ((size_t)max_batch + 8) * sizeof(int64_t);
     uint64_t* ring;
     uint32_t lg;
     if (hipMalloc((void**)&L.desc, L.desc_cap) != hipSuccess ||

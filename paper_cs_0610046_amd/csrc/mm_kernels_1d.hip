@@ -1631,24 +1631,32 @@ __global__ __launch_bounds__(kChunkThreads) void k_crun(Job<T> job) {
 }
 
 // ================================================================ batched
-// Descriptors and tile prefix sums for a batch of S series, three passes:
+// Descriptors and per-path tile prefix sums for a batch of S series (the
+// path of a series -- tile kernel of lag 1..4, or chunk kernel -- comes
+// from the plan's strategy for its size class, batch_path), three passes:
 //  1. k_batched_count (G <= 1024 workgroups, contiguous ranges of `per`
-//     series, a multiple of 256): descriptors, each series' tile count (tile
-//     or chunk strategy by the planner's rule), written in place, and the
-//     workgroup's totals;
-//  2. k_batched_scan (one workgroup): exclusive scan of the G totals;
-//  3. k_batched_fix (G workgroups): each range's exclusive scan plus its
-//     offset, in place; entry S gets the total.
+//     series, a multiple of 256): descriptors, each series' tile count on
+//     every path (zero but on its own), written in place, and the
+//     workgroup's totals per path;
+//  2. k_batched_scan (one workgroup): exclusive scan of the G totals of
+//     every path;
+//  3. k_batched_fix (G workgroups): each range's exclusive scans plus their
+//     offsets, in place; entry S of each path gets its total.
 // (A single-workgroup scan over the series took 0.42 ms for 100,000.)
+// Layout of pre: path p's prefix array at pre + p (S + 1); the totals at
+// part = pre + kBatchNP (S + 1): part[p G + g], grand totals part[kBatchNP G + p].
 
 template <class T>
 __global__ __launch_bounds__(256) void k_batched_count(const T* d_in, const int64_t* in_off, const int64_t* wins,
                                                        const int64_t* out_off, int64_t S, T* d_max, T* d_min,
-                                                       Series<T>* descs, int64_t* pre_tile, int64_t* pre_chunk,
-                                                       int64_t* part, int64_t per, int64_t run) {
-  __shared__ int64_t rt[4], rc[4];
+                                                       Series<T>* descs, int64_t* pre, BatchPlan plan, int64_t per) {
+  constexpr int NP = kBatchNP;
+  __shared__ int64_t red[NP][4];
   const int64_t k0 = (int64_t)blockIdx.x * per;
-  int64_t st = 0, sc = 0;
+  const int64_t run = (int64_t)plan.run_subtiles * kTileOut;
+  int64_t tot[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) tot[q] = 0;
   for (int64_t j = 0; j < per / 256; ++j) {
     const int64_t k = k0 + j * 256 + threadIdx.x;
     if (k >= S) break;
@@ -1663,103 +1671,106 @@ __global__ __launch_bounds__(256) void k_batched_count(const T* d_in, const int6
     d.omin = d_min ? d_min + out_off[k] : nullptr;
     d.carry = nullptr;
     descs[k] = d;
-    int64_t ct = 0, cc = 0;
-    if (w >= 1 && n > 0) {
-      if (w <= kTileMaxW) ct = run_count(n, w, run);
-      else cc = chunk_count(n, w);
+    const int path = batch_path(plan, n, w);
+    const int64_t c = batch_tiles(path, n, w, run);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int64_t v = q == path ? c : 0;
+      pre[q * (S + 1) + k] = v;
+      tot[q] += v;
     }
-    pre_tile[k] = ct;
-    pre_chunk[k] = cc;
-    st += ct;
-    sc += cc;
   }
   // workgroup totals
-  for (int d = 32; d >= 1; d >>= 1) {
-    st += __shfl_xor(st, d, 64);
-    sc += __shfl_xor(sc, d, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    rt[threadIdx.x >> 6] = st;
-    rc[threadIdx.x >> 6] = sc;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    for (int d = 32; d >= 1; d >>= 1) tot[q] += __shfl_xor(tot[q], d, 64);
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = tot[q];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = rt[0] + rt[1] + rt[2] + rt[3];
-    part[2 * blockIdx.x + 1] = rc[0] + rc[1] + rc[2] + rc[3];
+  if (threadIdx.x < NP) {
+    const int q = threadIdx.x;
+    int64_t* part = pre + NP * (S + 1);
+    part[(int64_t)q * gridDim.x + blockIdx.x] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
   }
 }
 
-// Exclusive scan of the G (<= 1024) workgroup totals, in place; entries 2G,
-// 2G+1 get the grand totals.
+// Exclusive scan of the G (<= 1024) workgroup totals of every path, in
+// place; part[kBatchNP G + p] gets path p's grand total.
 __global__ __launch_bounds__(1024) void k_batched_scan(int G, int64_t* part) {
-  __shared__ int64_t st[1024], sc[1024];
+  constexpr int NP = kBatchNP;
+  __shared__ int64_t sc[NP][1024];
   const int tid = threadIdx.x;
-  const int64_t a = tid < G ? part[2 * tid] : 0, c = tid < G ? part[2 * tid + 1] : 0;
-  st[tid] = a;
-  sc[tid] = c;
+  int64_t own[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    own[q] = tid < G ? part[q * G + tid] : 0;
+    sc[q][tid] = own[q];
+  }
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {
-    const int64_t xa = tid >= d ? st[tid - d] : 0, xc = tid >= d ? sc[tid - d] : 0;
+    int64_t x[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) x[q] = tid >= d ? sc[q][tid - d] : 0;
     __syncthreads();
-    st[tid] += xa;
-    sc[tid] += xc;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) sc[q][tid] += x[q];
     __syncthreads();
   }
-  if (tid < G) {
-    part[2 * tid] = st[tid] - a;
-    part[2 * tid + 1] = sc[tid] - c;
-  }
-  if (tid == 1023) {
-    part[2 * G] = st[1023];
-    part[2 * G + 1] = sc[1023];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    if (tid < G) part[q * G + tid] = sc[q][tid] - own[q];
+    if (tid == 1023) part[NP * G + q] = sc[q][1023];
   }
 }
 
-// Each workgroup's range: exclusive scan of its counts plus its offset
+// Each workgroup's range: exclusive scans of its counts plus its offsets
 // (per / 256 consecutive series per thread, read twice).
-__global__ __launch_bounds__(256) void k_batched_fix(int64_t S, int G, int64_t per, int64_t* pre_tile,
-                                                     int64_t* pre_chunk, const int64_t* part) {
-  __shared__ int64_t wt[4], wc[4];
+__global__ __launch_bounds__(256) void k_batched_fix(int64_t S, int G, int64_t per, int64_t* pre) {
+  constexpr int NP = kBatchNP;
+  __shared__ int64_t wt[NP][4];
+  const int64_t* part = pre + NP * (S + 1);
   const int64_t PT = per / 256;
   const int64_t k0 = (int64_t)blockIdx.x * per + (int64_t)threadIdx.x * PT;
   const int64_t k1 = min(S, k0 + PT);
-  int64_t at = 0, ac = 0;
-  for (int64_t k = k0; k < k1; ++k) {
-    at += pre_tile[k];
-    ac += pre_chunk[k];
-  }
-  // inclusive scan of the thread totals over the wavefront, then across
-  // the four wavefronts
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int64_t it = at, ic = ac;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int64_t xt = __shfl_up(it, d, 64), xc = __shfl_up(ic, d, 64);
-    if (lane >= d) {
-      it += xt;
-      ic += xc;
+  int64_t acc[NP], inc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    acc[q] = 0;
+    for (int64_t k = k0; k < k1; ++k) acc[q] += pre[q * (S + 1) + k];
+    // inclusive scan of the thread totals over the wavefront
+    inc[q] = acc[q];
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t x = __shfl_up(inc[q], d, 64);
+      if (lane >= d) inc[q] += x;
     }
-  }
-  if (lane == 63) {
-    wt[wv] = it;
-    wc[wv] = ic;
+    if (lane == 63) wt[q][wv] = inc[q];
   }
   __syncthreads();
-  int64_t bt = part[2 * blockIdx.x], bc = part[2 * blockIdx.x + 1];
-  for (int q = 0; q < wv; ++q) {
-    bt += wt[q];
-    bc += wc[q];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int64_t b = part[q * G + blockIdx.x];
+    for (int o = 0; o < wv; ++o) b += wt[q][o];
+    int64_t r = b + inc[q] - acc[q];  // exclusive
+    int64_t* a = pre + q * (S + 1);
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t v = a[k];
+      a[k] = r;
+      r += v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a[S] = part[NP * G + q];
   }
-  int64_t rt = bt + it - at, rc = bc + ic - ac;  // exclusive
-  for (int64_t k = k0; k < k1; ++k) {
-    const int64_t vt = pre_tile[k], vc = pre_chunk[k];
-    pre_tile[k] = rt;
-    pre_chunk[k] = rc;
-    rt += vt;
-    rc += vc;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    pre_tile[S] = part[2 * G];
-    pre_chunk[S] = part[2 * G + 1];
+}
+
+// Autotuner input: a pseudo-random pattern (a hashed position, small
+// integers of the element type).
+template <class T> __global__ void k_tune_fill(T* a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u;
+    h ^= h >> 15;
+    h *= 0x85EBCA77u;
+    h ^= h >> 13;
+    gstore(a + i, (T)(h & 0x3FFF));
   }
 }
 
@@ -1911,8 +1922,10 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
       }
     } else if (strategy == kStratTile3 || strategy == kStratTile4) {
       // windows ending three or four sub-tiles after they start
+      // (described series: the setup sends only such windows here)
       const int L = strategy == kStratTile3 ? 3 : 4;
-      if (a.w <= (L - 1) * (int64_t)kTileOut || a.w > L * (int64_t)kTileOut) return hipErrorInvalidValue;
+      if (a.mode != kJobDescs && (a.w <= (L - 1) * (int64_t)kTileOut || a.w > L * (int64_t)kTileOut))
+        return hipErrorInvalidValue;
       if (a.mode == kJobOne) {
         if (L == 3) hipLaunchKernelGGL((k_tile<kJobOne, T, false, 3>), g, dim3(kTileThreads), 0, st, j);
         else hipLaunchKernelGGL((k_tile<kJobOne, T, false, 4>), g, dim3(kTileThreads), 0, st, j);
@@ -1920,15 +1933,16 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
         if (L == 3) hipLaunchKernelGGL((k_tile<kJobRows, T, false, 3>), g, dim3(kTileThreads), 0, st, j);
         else hipLaunchKernelGGL((k_tile<kJobRows, T, false, 4>), g, dim3(kTileThreads), 0, st, j);
       } else {
-        return hipErrorInvalidValue;
+        if (L == 3) hipLaunchKernelGGL((k_tile<kJobDescs, T, false, 3>), g, dim3(kTileThreads), 0, st, j);
+        else hipLaunchKernelGGL((k_tile<kJobDescs, T, false, 4>), g, dim3(kTileThreads), 0, st, j);
       }
     } else if (strategy == kStratTile2) {
       // the two-sub-tile emission lag needs every window to end past its
       // own sub-tile and at most two sub-tiles on
-      if (a.w <= kTileMaxW || a.w > kTileMaxW2) return hipErrorInvalidValue;
+      if (a.mode != kJobDescs && (a.w <= kTileMaxW || a.w > kTileMaxW2)) return hipErrorInvalidValue;
       if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T, false, 2>), g, dim3(kTileThreads), 0, st, j);
       else if (a.mode == kJobRows) hipLaunchKernelGGL((k_tile<kJobRows, T, false, 2>), g, dim3(kTileThreads), 0, st, j);
-      else return hipErrorInvalidValue;
+      else hipLaunchKernelGGL((k_tile<kJobDescs, T, false, 2>), g, dim3(kTileThreads), 0, st, j);
     } else if (strategy == kStratTile) {
       if (a.mode != kJobDescs && a.w > kTileMaxW) return hipErrorInvalidValue;
       if (a.mode == kJobOne) hipLaunchKernelGGL((k_tile<kJobOne, T>), g, dim3(kTileThreads), 0, st, j);
@@ -1947,27 +1961,36 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
   });
 }
 
+hipError_t launch_tune_fill(int dtype, void* a, int64_t n, hipStream_t st) {
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tune_fill<T>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, st,
+                       (T*)a, n);
+    return hipGetLastError();
+  });
+}
+
 hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
                                 const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
-                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st, int64_t run) {
+                                int64_t* pre, const BatchPlan& plan, hipStream_t st) {
   return dispatch(dtype, [&](auto* p) {
     using T = std::remove_pointer_t<decltype(p)>;
     if (S <= 0) return hipSuccess;
+    if (plan.run_subtiles < 1) return hipErrorInvalidValue;
     // series per workgroup: a multiple of 256, at least 1024, at most
     // kBatchMaxGroups workgroups
     int64_t per = (S + kBatchMaxGroups - 1) / kBatchMaxGroups;
     per = std::max<int64_t>(1024, (per + 255) / 256 * 256);
     const int64_t G = (S + per - 1) / per;
-    int64_t* part = pre_chunk + (S + 1);  // 2G + 2 entries after the two prefix arrays
     hipLaunchKernelGGL(k_batched_count<T>, dim3((unsigned)G), dim3(256), 0, st, (const T*)d_in, in_off, wins,
-                       out_off, S, (T*)d_max, (T*)d_min, (Series<T>*)descs, pre_tile, pre_chunk, part, per, run);
+                       out_off, S, (T*)d_max, (T*)d_min, (Series<T>*)descs, pre, plan, per);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batched_scan, dim3(1), dim3(1024), 0, st, (int)G, part);
+    hipLaunchKernelGGL(k_batched_scan, dim3(1), dim3(1024), 0, st, (int)G, pre + kBatchNP * (S + 1));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batched_fix, dim3((unsigned)G), dim3(256), 0, st, S, (int)G, per, pre_tile, pre_chunk,
-                       (const int64_t*)part);
+    hipLaunchKernelGGL(k_batched_fix, dim3((unsigned)G), dim3(256), 0, st, S, (int)G, per, pre);
     return hipGetLastError();
   });
 }

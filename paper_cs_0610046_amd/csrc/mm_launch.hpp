@@ -46,8 +46,33 @@ __host__ __device__ inline int64_t crun_chunks(int64_t n, int64_t w) {
   return (last / w) * K + (last % w) / C + 1;
 }
 
-// Batched strategy selection happens on the device with the same rule as the
-// host planner's default: tile for w <= kTileMaxW, chunk otherwise.
+// Batched calls: every series falls in a size class by its window (w <=
+// 2048, <= 4096, <= 8192, longer) and its length (n < 2^16, < 2^20,
+// longer); a plan gives each class a strategy: the tile kernel of the lag
+// that fits the window (classes up to 8192) or the chunk kernel.  The
+// series of one path share a launch: kBatchNP tile-prefix arrays, one per
+// path (tile lag 1..4, chunk).
+constexpr int kBatchWClasses = 4, kBatchNClasses = 3, kBatchNP = 5;
+constexpr int kBatchChunkPath = 4;
+enum BatchStrategy : uint8_t { kBatchTile = 0, kBatchChunk = 1 };
+struct BatchPlan {
+  uint8_t strat[kBatchWClasses][kBatchNClasses];  // BatchStrategy per class
+  int32_t run_subtiles;                             // tile of the tile paths, in sub-tiles
+};
+__host__ __device__ inline int batch_wclass(int64_t w) {
+  return w <= 2048 ? 0 : (w <= 4096 ? 1 : (w <= 8192 ? 2 : 3));
+}
+__host__ __device__ inline int batch_nclass(int64_t n) { return n < (1 << 16) ? 0 : (n < (1 << 20) ? 1 : 2); }
+// Which launch serves a series: 0..3 the tile kernel of lag 1..4, 4 the
+// chunk kernel; -1 when the series has no complete window.
+__host__ __device__ inline int batch_path(const BatchPlan& p, int64_t n, int64_t w) {
+  if (w < 1 || n < w) return -1;
+  const int wc = batch_wclass(w);
+  if (wc == 3 || p.strat[wc][batch_nclass(n)] == kBatchChunk) return kBatchChunkPath;
+  return w <= 2048 ? 0 : (int)((w - 1) / 2048);  // lag 1; 2 (<= 4096); 3 (<= 6144); 4 (<= 8192)
+}
+// Tiles of a series on its path: runs of `run` windows, or chunks.
+__host__ __device__ inline int64_t batch_tiles(int path, int64_t n, int64_t w, int64_t run);
 
 // Batched envelopes: a series of at most kEnvShortN samples with radius at
 // most kEnvShortR is served whole by one wavefront (k_env_short); the others
@@ -95,6 +120,11 @@ inline int long_col_v(int64_t w) {
   return w <= 65536 && (whole || K <= 3) ? kColVShort : kChunkV;
 }
 inline int64_t long_chunk_max(int64_t w) { return int64_t(kChunkThreads) * long_col_v(w); }
+
+__host__ __device__ inline int64_t batch_tiles(int path, int64_t n, int64_t w, int64_t run) {
+  if (path < 0) return 0;
+  return path == kBatchChunkPath ? chunk_count(n, w) : run_count(n, w, run);
+}
 
 // Type-erased description of a 1-D launch (converted to Job<T> inside).
 struct JobArgs {
@@ -157,13 +187,19 @@ hipError_t launch_tile_series(int dtype, JobArgs a, hipStream_t st);
 hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st);
 
 // Batched setup: fills S descriptors (bytes: S * series_bytes()) and the
-// per-strategy tile prefix sums pre_tile / pre_chunk (S + 1 entries each);
-// the 2 * kBatchMaxGroups + 2 entries after pre_chunk[S] are scratch for
-// the per-workgroup totals.
+// kBatchNP per-path tile prefix sums pre + p (S + 1), p = 0..kBatchNP-1
+// (batch_pre_len(S) entries in all, the per-workgroup totals included).
 constexpr int64_t kBatchMaxGroups = 1024;
+inline int64_t batch_pre_len(int64_t S) { return kBatchNP * (S + 1) + kBatchNP * (kBatchMaxGroups + 1); }
 hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_off, const int64_t* wins,
                                 const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
-                                int64_t* pre_tile, int64_t* pre_chunk, hipStream_t st, int64_t run = kRunBatched);
+                                int64_t* pre, const BatchPlan& plan, hipStream_t st);
+
+// The autotuner's input: n elements of a pseudo-random pattern.
+hipError_t launch_tune_fill(int dtype, void* a, int64_t n, hipStream_t st);
+// The batched plan the planner uses for dtype (tuned or default, with the
+// experiment overrides), for launches made outside mm_abi.cpp.
+BatchPlan batch_plan_for(int dtype);
 
 // A stream push that completes no window: new carry = last min(n, w-1)
 // samples of (a[0..na) ++ b).

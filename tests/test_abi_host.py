@@ -85,8 +85,11 @@ def test_argument_errors_without_gpu(lib):
 
 def test_tuning_table_and_autotune_arguments(lib):
     t = binding.maxmin_tuning(np.float32)
-    assert t == {"tile_run_subtiles": 16, "rows_run_subtiles": 16, "chunk_ranges_one_chunk": 16,
-                 "chunk_ranges_long": 0, "long_window_strategy": "chunk", "measured": False}
+    plan = t.pop("batched_plan")
+    assert t == {"tile_run_subtiles": 4, "tile_run_subtiles_long": 64, "rows_run_subtiles": 16,
+                 "chunk_ranges_one_chunk": 16, "chunk_ranges_long": 0, "long_window_strategy": "chunk",
+                 "batched_tile_subtiles": 1, "measured": False}
+    assert len(plan) == 9 and set(plan.values()) == {"tile"}  # default: the tile kernel for every class
     assert lib.maxmin_autotune(9, 0, None) == binding.MAXMIN_EINVAL
     assert lib.maxmin_autotune(0, 1000, None) == binding.MAXMIN_EINVAL  # below 2^20, checked before any device call
     assert lib.maxmin_tuning(9, None) == binding.MAXMIN_EINVAL

@@ -301,3 +301,36 @@ def test_batched_graph_replay_matches_eager():
             assert_bits_equal(to_host(outs[1], np.float32), emn, "replay %d min" % rep)
             del y
     mm.maxmin_check_stream(s)
+
+
+@pytest.mark.parametrize("plan", ["tile", "chunk"])
+@pytest.mark.parametrize("run", ["1", "2", "4"])
+def test_batched_plans(plan, run, monkeypatch):
+    """Every batched plan the autotuner can choose gives the oracle's bits:
+    all size classes on the tile kernel of their lag or on the chunk
+    kernel, batched tiles of 1, 2 and 4 sub-tiles; series at any element
+    offset, lengths across 2^16 and 2^20, windows to 12000, empty series
+    and w > n."""
+    import torch
+    monkeypatch.setenv("MAXMIN_BATCH_PLAN", plan)
+    monkeypatch.setenv("MAXMIN_BATCH_RUN", run)
+    rng = synth.rng_for("tests", 109)
+    for dt in (np.float32, np.float64, np.uint16):
+        S = 60
+        lens = np.floor(np.exp(rng.uniform(0, np.log(80000), S))).astype(np.int64)
+        lens[:4] = [(1 << 20) + 3, 70001, 0, 5]
+        wins = rng.integers(1, 2100, S).astype(np.int64)
+        wins[::3] = rng.integers(2049, 12000, wins[::3].size)
+        wins[3] = 9
+        offs = np.zeros(S + 1, np.int64)
+        np.cumsum(lens, out=offs[1:])
+        packed = gen(int(offs[-1]), dt, rng, "walk")
+        oo = mm.maxmin_out_offsets(offs, wins)
+        note("batched plan=%s run=%s dt=%s total=%d" % (plan, run, np.dtype(dt).name, offs[-1]))
+        d_off, d_w, d_oo = (torch.from_numpy(v).cuda() for v in (offs, wins, oo))
+        dmx, dmn = mm.maxmin_filter_batched(to_dev(packed), d_off, d_w, d_oo)
+        torch.cuda.synchronize()
+        mm.maxmin_check_stream()
+        _, emx, emn = oracle.batched(packed, offs, wins)
+        assert_bits_equal(to_host(dmx, dt), emx, "batched plan=%s run=%s max" % (plan, run))
+        assert_bits_equal(to_host(dmn, dt), emn, "batched plan=%s run=%s min" % (plan, run))
