@@ -170,20 +170,24 @@ bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols, bool one_output) {
 bool stream_cols_2d(int dtype, int64_t w_rows) { return w_rows < 16 || (dsize(dtype) == 2 && w_rows <= 64); }
 
 // Long windows of a single series (more than one chunk per block): the
-// two-pass column kernels, except full 4096-element chunks with at most 8
-// per block, where the look-back kernel was faster.  On MI355X (n = 2^28
-// float32), columns (4096-element chunks) / look-back: w = 4097 1.80 / 2.24
-// ms, 5000 1.14 / 1.98, 6500 1.59 / 1.73, 8192 1.04 / 0.83, 16384 1.02 /
-// 0.85, 65536 0.98 / 0.97, 131072 0.89 / 1.04, 200000 1.29 / 2.03, 2^20
-// 0.95 / 0.99; with 2048-element chunks the columns took 0.96 ms at 16384
-// and 0.94 ms at 65536 (long_chunk_max).  MAXMIN_LONG_LOOKBACK=1 / =0
-// forces either (experiments, tests).
+// one-pass column kernel; the look-back chunk kernel only when
+// MAXMIN_LONG_LOOKBACK=1 asks for it (experiments, tests).  On MI355X (n =
+// 2^28 float32) the one-pass kernel matched or beat look-back everywhere
+// (w = 16384 0.84 / 0.85 ms, 32768 0.85 / 0.91 ms) and the two passes
+// (aggregates, then columns) everywhere (w = 8193 1.15 / 1.56 ms, 20000
+// 0.77 / 0.90, 65536 0.77 / 0.94, 2^20 0.89 / 0.94).
+// The two passes instead of the one-pass kernel: MAXMIN_LONG_ONEPASS=0
+// (experiments, tests); also where a cooperative launch cannot hold one
+// column group.
+bool long_onepass() {
+  const char* e = getenv("MAXMIN_LONG_ONEPASS");
+  return !(e && !strcmp(e, "0"));
+}
+
 bool long_lookback(int64_t w) {
+  (void)w;
   const char* e = getenv("MAXMIN_LONG_LOOKBACK");
-  if (e && !strcmp(e, "1")) return true;
-  if (e && !strcmp(e, "0")) return false;
-  const int64_t K = (w + mm::kChunkMax - 1) / mm::kChunkMax, C = (w + K - 1) / K;
-  return C == mm::kChunkMax && K <= 8;
+  return e && !strcmp(e, "1");
 }
 
 // Which tile kernel a single series or a row pass of window w runs.
@@ -215,6 +219,8 @@ struct Workspace {
   size_t env_bytes = 0;
   void* agg = nullptr;  // long windows: chunk maxima and minima
   size_t agg_bytes = 0;
+  uint64_t* rec = nullptr;  // long windows, one pass: tagged chunk records (zeroed when allocated)
+  size_t rec_bytes = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -332,6 +338,19 @@ int ensure_buf(Workspace* ws, void** buf, size_t* have, size_t bytes) {
   return MAXMIN_OK;
 }
 int ensure_tmp(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp, &ws->tmp_bytes, bytes); }
+// Record buffer of the one-pass long-window kernel: zeroed when allocated
+// (tag 0 never validates; every later record carries a launch epoch).
+int ensure_rec(Workspace* ws, size_t bytes) {
+  if (ws->rec && ws->rec_bytes >= bytes) return MAXMIN_OK;
+  void* p = ws->rec;
+  int r = ensure_buf(ws, &p, &ws->rec_bytes, bytes);
+  ws->rec = (uint64_t*)p;
+  if (r) return r;
+  hipError_t e = hipMemset(ws->rec, 0, bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipMemset(long-window records)");
+  return MAXMIN_OK;
+}
 int ensure_tmp2(Workspace* ws, size_t bytes) { return ensure_buf(ws, &ws->tmp2, &ws->tmp2_bytes, bytes); }
 
 // Ticket ranges for a single-series chunk launch (0, 1, 8, 16 or 32), for
@@ -392,9 +411,16 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     Workspace* ws = nullptr;
     int r = get_ws(st, &ws);
     if (r) return r;
-    const int64_t nch = mm::chunk_count(a.n, a.w, mm::long_chunk_max(a.w));
-    if ((r = ensure_buf(ws, &ws->agg, &ws->agg_bytes, (size_t)std::max<int64_t>(1, 2 * nch) * dsize(dt)))) return r;
-    e = mm::launch_long(dt, a, ws->agg, st);
+    e = hipErrorNotSupported;
+    if (long_onepass()) {
+      if ((r = ensure_rec(ws, (size_t)std::max<int64_t>(1, mm::long1_records(a.n, a.w)) * 32))) return r;
+      e = mm::launch_long1(dt, a, ws->rec, ws->ctl, st);
+    }
+    if (e == hipErrorNotSupported) {
+      const int64_t nch = mm::chunk_count(a.n, a.w, mm::long_chunk_max(a.w));
+      if ((r = ensure_buf(ws, &ws->agg, &ws->agg_bytes, (size_t)std::max<int64_t>(1, 2 * nch) * dsize(dt)))) return r;
+      e = mm::launch_long(dt, a, ws->agg, st);
+    }
   } else {
     Workspace* ws = nullptr;
     int r = get_ws(st, &ws);
@@ -439,6 +465,13 @@ int stream_lookback_state(hipStream_t stream, int64_t ntiles, uint64_t** ring, u
 }
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 BatchPlan batch_plan_for(int dtype) { return batch_plan(dtype); }
+int long_col_v_override() {
+  static const int v = [] {
+    const char* e = getenv("MAXMIN_LONG_V");
+    return e && !strcmp(e, "8") ? 8 : (e && !strcmp(e, "16") ? 16 : 0);
+  }();
+  return v;
+}
 }  // namespace mm
 
 struct maxmin_stream {

@@ -1172,6 +1172,184 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col(Series<T> s, const 
   }
 }
 
+// One pass (k_chunk_col1): the same columns, without the aggregate pass.
+// Each workgroup publishes its chunk's max and min (a tagged record, as the
+// look-back kernel's) as soon as its scans give them, and reads the chunks
+// between from its siblings' records: (b, 0..k-1) are published by the
+// range's other workgroups in the same step, (b-1, k+1..K-1) one step
+// earlier.  A range's first block needs the block before it, which the
+// previous range reaches only at its end, so every workgroup also publishes
+// its column's chunk of that block (loaded anyway; the previous range later
+// publishes the same values).  A workgroup publishes before it waits, and
+// waits only on records of its own step or earlier, so with every workgroup
+// resident (the launch is cooperative) every wait ends; one that outlasts
+// the spin limit sets the error word instead of hanging.
+template <class T, int V>
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_col1(Series<T> s, uint64_t* rec, Ctl* ctl) {
+  constexpr int64_t CM = int64_t(kChunkThreads) * V;
+  constexpr int NW = kChunkThreads / 64;
+  __shared__ ColLds<T, V> sm;
+  __shared__ T edge[NW];
+  __shared__ T pro[2][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t w = s.w, n = s.n;
+  const int64_t K = (w + CM - 1) / CM, C = (w + K - 1) / K;
+  const int64_t NB = (n + w - 1) / w;  // blocks, the last one partial
+  const int64_t k = blockIdx.x % K, R = gridDim.x / K, rr = blockIdx.x / K;
+  const int64_t per = (NB + R - 1) / R;
+  const int64_t b0 = rr * per, b1 = min(NB, b0 + per);
+  const int lenfull = (int)min(C, w - k * C);
+  const int r0 = tid * V;
+  const uint32_t ep = ld_agent32(&ctl->epoch);
+  T prev[V], cur[V];  // raw inputs of the column's previous chunk and of this one
+  if (b0 < b1) {
+    // (published also when this column has no chunk in block b0: a sibling
+    // with one may need it)
+    if (b0 >= 1) {
+      col_load<T, V>(s, (b0 - 1) * w + k * C, lenfull, prev);  // whole: it ends before block b0
+      T mx = Lim<T>::lo(), mn = Lim<T>::hi();
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (r0 + i < lenfull) {
+          mx = hmax(mx, prev[i]);
+          mn = hmin(mn, prev[i]);
+        }
+      for (int d = 32; d >= 1; d >>= 1) {
+        mx = hmax(mx, (T)__shfl_xor(mx, d, 64));
+        mn = hmin(mn, (T)__shfl_xor(mn, d, 64));
+      }
+      if (lane == 0) {
+        pro[0][wave] = mx;
+        pro[1][wave] = mn;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int q = 1; q < NW; ++q) {
+          mx = hmax(mx, pro[0][q]);
+          mn = hmin(mn, pro[1][q]);
+        }
+        publish<T>(rec + 4 * ((b0 - 1) * K + k), mx, mn, ep);
+      }
+    }
+  }
+  if (b0 < b1 && b0 * w + k * C < n) {
+    col_load<T, V>(s, b0 * w + k * C, (int)min((int64_t)lenfull, n - (b0 * w + k * C)), cur);
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t p0 = b * w + k * C;
+      if (p0 >= n) break;
+      const int len = (int)min((int64_t)lenfull, n - p0);
+      // the next chunk's loads fly while this one is computed
+      T nxt[V];
+      const int64_t p1 = p0 + w;
+      if (b + 1 < b1 && p1 < n) col_load<T, V>(s, p1, (int)min((int64_t)lenfull, n - p1), nxt);
+      const bool has_out = (p0 + len - 1) >= (w - 1);
+      if (s.carry != nullptr) {
+        const int64_t cs = n - min(n, w - 1);
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          if (r0 + i < len && p0 + r0 + i >= cs) gstore(s.carry + (p0 + r0 + i - cs), cur[i]);
+      }
+      // behind slot r: the previous chunk's slot r + 1 (the start of the
+      // window that ends at slot r), from this lane, the next lane, or the
+      // next wavefront's lane 0
+      if (lane == 0) edge[wave] = prev[0];
+      __syncthreads();
+      T nb = __shfl_down(prev[0], 1, 64);
+      if (lane == 63) nb = wave + 1 < NW ? edge[wave + 1] : T(0);
+      T ax[V], an[V], bx[V], bn[V];
+      const bool behind = b >= 1;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const bool vo = r0 + i < len;
+        ax[i] = vo ? cur[i] : Lim<T>::lo();
+        an[i] = vo ? cur[i] : Lim<T>::hi();
+        const bool vb = behind && r0 + i + 1 < lenfull;
+        const T h = i + 1 < V ? prev[i + 1 < V ? i + 1 : 0] : nb;
+        bx[i] = vb ? h : Lim<T>::lo();
+        bn[i] = vb ? h : Lim<T>::hi();
+      }
+#pragma unroll
+      for (int i = 1; i < V; ++i) {
+        ax[i] = hmax(ax[i - 1], ax[i]);
+        an[i] = hmin(an[i - 1], an[i]);
+      }
+#pragma unroll
+      for (int i = V - 2; i >= 0; --i) {
+        bx[i] = hmax(bx[i + 1], bx[i]);
+        bn[i] = hmin(bn[i + 1], bn[i]);
+      }
+      T epx = ax[V - 1], epn = an[V - 1], esx = bx[0], esn = bn[0], tx, tn;
+      wg_scan2<T>(epx, epn, esx, esn, tx, tn, sm);
+      // this chunk's max and min, for the siblings' windows
+      if (tid == 0) publish<T>(rec + 4 * (b * K + k), tx, tn, ep);
+      if (has_out && tid < 64) {
+        // (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
+        T prx = Lim<T>::lo(), prn = Lim<T>::hi(), sux = Lim<T>::lo(), sun = Lim<T>::hi();
+        for (int64_t j = tid; j < K; j += 64) {
+          if (j < k) {
+            T mx, mn;
+            fetch<T>(rec + 4 * (b * K + j), ep, mx, mn, ctl);
+            prx = hmax(prx, mx);
+            prn = hmin(prn, mn);
+          } else if (j > k && b >= 1) {
+            T mx, mn;
+            fetch<T>(rec + 4 * ((b - 1) * K + j), ep, mx, mn, ctl);
+            sux = hmax(sux, mx);
+            sun = hmin(sun, mn);
+          }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          prx = hmax(prx, (T)__shfl_xor(prx, d, 64));
+          prn = hmin(prn, (T)__shfl_xor(prn, d, 64));
+          sux = hmax(sux, (T)__shfl_xor(sux, d, 64));
+          sun = hmin(sun, (T)__shfl_xor(sun, d, 64));
+        }
+        if (tid == 0) {
+          sm.dep[0] = prx;
+          sm.dep[1] = prn;
+          sm.dep[2] = sux;
+          sm.dep[3] = sun;
+        }
+      }
+      __syncthreads();
+      if (has_out) {
+        const T prx = hmax(sm.dep[0], epx), prn = hmin(sm.dep[1], epn);
+        const T sux = hmax(sm.dep[2], esx), sun = hmin(sm.dep[3], esn);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const int r = r0 + i;
+          if (r < len) {
+            sm.xs[lds_idx<T>(r)] = hmax(hmax(bx[i], sux), hmax(prx, ax[i]));
+            sm.hs[lds_idx<T>(r)] = hmin(hmin(bn[i], sun), hmin(prn, an[i]));
+          }
+        }
+        __syncthreads();
+        const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
+        if (s.omax) chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+        if (s.omin) chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        prev[i] = cur[i];
+        cur[i] = nxt[i];
+      }
+    }
+  }
+  // the last workgroup out bumps the epoch (no record of this launch
+  // validates in the next one)
+  if (tid == 0) {
+    const uint32_t d = add_agent32(&ctl->done, 1u);
+    if (d == gridDim.x - 1) {
+      st_agent32(&ctl->done, 0u);
+      uint32_t e = ep + 1u;
+      if (e == 0u) e = 1u;
+      st_agent32(&ctl->epoch, e);
+    }
+  }
+}
+
 template <int MODE, class T>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk(Job<T> job) {
   __shared__ ChunkLds<T> sm;
@@ -1888,6 +2066,37 @@ static hipError_t launch_long_v(const Series<T>& s, int64_t nch, int64_t K, T* a
   hipLaunchKernelGGL((k_chunk_col<T, V>), dim3((unsigned)g2), dim3(kChunkThreads), 0, st, s, (const T*)ax,
                      (const T*)an);
   return hipGetLastError();
+}
+
+template <class T, int V>
+static hipError_t launch_long1_v(Series<T> s, int64_t K, uint64_t* rec, Ctl* ctl, hipStream_t st) {
+  // every workgroup resident: a multiple of K no larger than the device holds
+  const int64_t cap = occupancy_grid(k_chunk_col1<T, V>, kChunkThreads);
+  const int64_t g = cap / K * K;
+  if (g < K) return hipErrorNotSupported;  // fewer slots than one column group
+  void* args[] = {(void*)&s, (void*)&rec, (void*)&ctl};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_chunk_col1<T, V>), dim3((unsigned)g),
+                                    dim3(kChunkThreads), args, 0, st);
+}
+
+int64_t long1_records(int64_t n, int64_t w) {
+  const int64_t cmax = int64_t(kChunkThreads) * long1_col_v(w);
+  const int64_t K = (w + cmax - 1) / cmax;
+  return ((n + w - 1) / w) * K;
+}
+
+hipError_t launch_long1(int dtype, const JobArgs& a, uint64_t* rec, Ctl* ctl, hipStream_t st) {
+  const int V = long1_col_v(a.w);
+  const int64_t cmax = int64_t(kChunkThreads) * V;
+  const int64_t K = (a.w + cmax - 1) / cmax;
+  if (chunk_count(a.n, a.w, cmax) <= 0) return hipSuccess;
+  if (K < 2 || a.mode != kJobOne) return hipErrorInvalidValue;
+  return dispatch(dtype, [&](auto* p) {
+    using T = std::remove_pointer_t<decltype(p)>;
+    const Series<T> s = make_series<T>(a);
+    return V == kColVShort ? launch_long1_v<T, kColVShort>(s, K, rec, ctl, st)
+                           : launch_long1_v<T, kChunkV>(s, K, rec, ctl, st);
+  });
 }
 
 hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st) {

@@ -114,12 +114,22 @@ __host__ __device__ inline int64_t chunk_count(int64_t n, int64_t w, int64_t cma
 // 65536 0.94 / 0.97, but 40000 0.98 / 0.94, 262144 0.99 / 0.86 and 2^20
 // 1.17 / 0.94.
 constexpr int kColVShort = 8;
+int long_col_v_override();  // MAXMIN_LONG_V = 8 / 16 (experiments), else 0
 inline int long_col_v(int64_t w) {
+  if (const int v = long_col_v_override()) return v;
   const int64_t K = (w + kChunkMax - 1) / kChunkMax;
   const bool whole = K * kChunkMax == w;
   return w <= 65536 && (whole || K <= 3) ? kColVShort : kChunkV;
 }
 inline int64_t long_chunk_max(int64_t w) { return int64_t(kChunkThreads) * long_col_v(w); }
+// The one-pass kernel (k_chunk_col1): chunks of 2048 only while a window
+// spans at most three 4096-element chunks.  On MI355X (n = 2^28 float32),
+// 2048 / 4096: w = 8193 1.17 / 1.20 ms, 10000 0.88 / 1.04, 20000 0.88 /
+// 0.77, 65536 0.87 / 0.77, 131072 0.91 / 0.78, 2^20 1.26 / 0.89.
+inline int long1_col_v(int64_t w) {
+  if (const int v = long_col_v_override()) return v;
+  return (w + kChunkMax - 1) / kChunkMax <= 3 ? kColVShort : kChunkV;
+}
 
 __host__ __device__ inline int64_t batch_tiles(int path, int64_t n, int64_t w, int64_t run) {
   if (path < 0) return 0;
@@ -185,6 +195,13 @@ hipError_t launch_tile_series(int dtype, JobArgs a, hipStream_t st);
 // then one column of chunks per workgroup (no look-back, no re-read of the
 // chunk w back).
 hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st);
+// The same in one pass (no aggregate pass): each column workgroup publishes
+// its chunk's max and min as tagged records in rec (4 words per chunk,
+// long1_records(n, w) chunks) and reads its siblings'; needs the stream's
+// control words (epoch) and a cooperative launch (hipErrorNotSupported when
+// a column group does not fit on the device).
+int64_t long1_records(int64_t n, int64_t w);
+hipError_t launch_long1(int dtype, const JobArgs& a, uint64_t* rec, Ctl* ctl, hipStream_t st);
 
 // Batched setup: fills S descriptors (bytes: S * series_bytes()) and the
 // kBatchNP per-path tile prefix sums pre + p (S + 1), p = 0..kBatchNP-1

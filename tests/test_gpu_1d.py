@@ -118,14 +118,17 @@ def test_misaligned_outputs():
                 assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "min offsets %d/%d/%d" % (oi, ox, on))
 
 
-@pytest.mark.parametrize("lookback", ["0", "1"], ids=["columns", "lookback"])
+@pytest.mark.parametrize("path", ["onepass", "twopass", "lookback"])
 @pytest.mark.parametrize("strategy", [mm.STRATEGY_AUTO, mm.STRATEGY_CHUNK, mm.STRATEGY_RUN], ids=["auto", "chunk", "run"])
-def test_large_windows(strategy, lookback, monkeypatch):
-    """Windows of more than one chunk: the two-pass column kernels and
-    (MAXMIN_LONG_LOOKBACK=1) the look-back chunk kernel; every dtype, block
-    counts from one to dozens with a ragged last block, and a window
-    longer than 256 chunks."""
+def test_large_windows(strategy, path, monkeypatch):
+    """Windows of more than one chunk: the one-pass column kernel (records
+    between sibling workgroups), the two passes (MAXMIN_LONG_ONEPASS=0:
+    aggregates, then columns) and the look-back chunk kernel
+    (MAXMIN_LONG_LOOKBACK=1); every dtype, block counts from one to dozens
+    with a ragged last block, and a window longer than 256 chunks."""
+    lookback = "1" if path == "lookback" else "0"
     monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", lookback)
+    monkeypatch.setenv("MAXMIN_LONG_ONEPASS", "0" if path == "twopass" else "1")
     rng = synth.rng_for("tests", 104)
     a = gen(300000, np.float32, rng, "walk")
     for w in (2048, 4096, 4100, 65536, 100000, 299999, 300000):
@@ -220,17 +223,20 @@ def test_repeatable_bits():
             assert torch.equal(r[0], r0[0]) and torch.equal(r[1], r0[1])
 
 
-@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000, 7000, 9000, 20000, 40000])
+@pytest.mark.parametrize("w", [1, 2, 64, 512, 1024, 1025, 3000, 5000, 7000, 9000, 20000, 40000, 65536])
 def test_stream_chunks_equal_one_shot(w, monkeypatch):
-    """Every dtype.  w = 9000 takes the two-pass kernels with 2048-element
-    chunks, w = 40000 with 4096-element chunks (k_chunk_col<T, 16>), w =
-    20000 is forced onto the look-back chunk kernel."""
+    """Every dtype.  w = 9000 and 65536 take the one-pass kernel (2048- and
+    4096-element chunks), w = 40000 the two passes (forced; 4096-element
+    chunks, k_chunk_col<T, 16>), w = 20000 the look-back chunk kernel
+    (forced)."""
     if w == 20000:
         monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", "1")
+    if w == 40000:
+        monkeypatch.setenv("MAXMIN_LONG_ONEPASS", "0")
     import torch
     rng = synth.rng_for("tests", 106)
     for dt in DTS:
-        a = gen(40000 if w < 40000 else 250000, dt, rng, "walk")
+        a = gen(40000 if w < 40000 else 300000, dt, rng, "walk")
         st = mm.maxmin_stream_create(to_dev(a[:1]).dtype, w)
         ost = oracle.Stream(dt, w)
         pos = 0

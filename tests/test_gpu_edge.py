@@ -7,7 +7,8 @@ INT32_MAX, uint16 0 / 65535).  These series (``synth.edge_series``: runs of
 such values and of values uniform over the bit patterns, long enough that
 whole windows hold one extreme value) go through every kernel: the tile
 kernel at each lag (w <= 2048, <= 4096, <= 6144, <= 8192), the look-back
-chunk kernel, the two long-window passes (both chunk sizes), chunk runs,
+chunk kernel, the one-pass long-window kernel and the two passes (both
+chunk sizes), chunk runs,
 batched tiles and chunks, stream pushes, both 2-D paths and every column
 pass, the arg filter's three paths, envelopes and morphology.
 """
@@ -24,13 +25,15 @@ pytestmark = pytest.mark.gpu
 DTS = [np.float32, np.float64, np.int32, np.uint16]
 IDS = [np.dtype(d).name for d in DTS]
 
-# (window, strategy, MAXMIN_LONG_LOOKBACK) -> the kernel each one reaches
+# (window, strategy, MAXMIN_LONG_LOOKBACK or "2" for the two passes) -> the
+# kernel each one reaches
 CASES_1D = [
     (1, mm.STRATEGY_AUTO, None), (2, mm.STRATEGY_AUTO, None), (17, mm.STRATEGY_AUTO, None),
     (256, mm.STRATEGY_AUTO, None), (1500, mm.STRATEGY_AUTO, None), (2048, mm.STRATEGY_AUTO, None),  # tile, lag 1
     (3000, mm.STRATEGY_AUTO, None), (4096, mm.STRATEGY_AUTO, None),                                 # lag 2
     (5000, mm.STRATEGY_AUTO, None), (8000, mm.STRATEGY_AUTO, None),                                 # lag 3, 4
-    (9000, mm.STRATEGY_AUTO, "0"), (40000, mm.STRATEGY_AUTO, "0"), (65536, mm.STRATEGY_AUTO, "0"),  # two passes
+    (9000, mm.STRATEGY_AUTO, "0"), (40000, mm.STRATEGY_AUTO, "0"), (65536, mm.STRATEGY_AUTO, "0"),  # one pass
+    (9000, mm.STRATEGY_AUTO, "2"), (65536, mm.STRATEGY_AUTO, "2"),                                 # two passes
     (16384, mm.STRATEGY_AUTO, "1"), (20000, mm.STRATEGY_AUTO, "1"),                                 # look-back
     (300, mm.STRATEGY_CHUNK, None), (3000, mm.STRATEGY_CHUNK, None),                                # one-chunk
     (300, mm.STRATEGY_RUN, None), (20000, mm.STRATEGY_RUN, None),                                   # chunk runs
@@ -47,9 +50,11 @@ def test_edge_values_1d_every_kernel(dt, monkeypatch):
     a = _series(250003, dt, 900)
     x = to_dev(a)
     for w, strat, lb in CASES_1D:
-        if lb is None:
-            monkeypatch.delenv("MAXMIN_LONG_LOOKBACK", raising=False)
-        else:
+        monkeypatch.delenv("MAXMIN_LONG_LOOKBACK", raising=False)
+        monkeypatch.delenv("MAXMIN_LONG_ONEPASS", raising=False)
+        if lb == "2":  # the two passes
+            monkeypatch.setenv("MAXMIN_LONG_ONEPASS", "0")
+        elif lb is not None:
             monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", lb)
         note("edge 1d dt=%s w=%d strategy=%d lookback=%s" % (np.dtype(dt).name, w, strat, lb))
         mm.maxmin_set_strategy(strat)
@@ -95,7 +100,8 @@ def test_edge_values_batched(dt):
 @pytest.mark.parametrize("w", [64, 3000, 20000])
 def test_edge_values_stream(dt, w):
     """Pushes of random sizes (carry only, one window, many windows); w =
-    20000 reaches the two-pass kernels with 4096-element chunks."""
+    20000 reaches the one-pass long-window kernel with 4096-element
+    chunks."""
     import torch
     rng = np.random.default_rng(903)
     a = _series(90000, dt, 904)
