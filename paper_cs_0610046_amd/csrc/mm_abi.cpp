@@ -413,7 +413,7 @@ int run_series(int dt, JobArgs a, hipStream_t st, const char* what) {
     if (r) return r;
     e = hipErrorNotSupported;
     if (long_onepass()) {
-      if ((r = ensure_rec(ws, (size_t)std::max<int64_t>(1, mm::long1_records(a.n, a.w)) * 32))) return r;
+      if ((r = ensure_rec(ws, (size_t)std::max<int64_t>(1, mm::long1_records(dt, a.n, a.w)) * 32))) return r;
       e = mm::launch_long1(dt, a, ws->rec, ws->ctl, st);
     }
     if (e == hipErrorNotSupported) {

@@ -2079,14 +2079,16 @@ static hipError_t launch_long1_v(Series<T> s, int64_t K, uint64_t* rec, Ctl* ctl
                                     dim3(kChunkThreads), args, 0, st);
 }
 
-int64_t long1_records(int64_t n, int64_t w) {
-  const int64_t cmax = int64_t(kChunkThreads) * long1_col_v(w);
+static size_t elem_size(int dtype) { return dtype == 1 ? 8 : (dtype == 3 ? 2 : 4); }
+
+int64_t long1_records(int dtype, int64_t n, int64_t w) {
+  const int64_t cmax = int64_t(kChunkThreads) * long1_col_v(w, elem_size(dtype));
   const int64_t K = (w + cmax - 1) / cmax;
   return ((n + w - 1) / w) * K;
 }
 
 hipError_t launch_long1(int dtype, const JobArgs& a, uint64_t* rec, Ctl* ctl, hipStream_t st) {
-  const int V = long1_col_v(a.w);
+  const int V = long1_col_v(a.w, elem_size(dtype));
   const int64_t cmax = int64_t(kChunkThreads) * V;
   const int64_t K = (a.w + cmax - 1) / cmax;
   if (chunk_count(a.n, a.w, cmax) <= 0) return hipSuccess;

@@ -126,9 +126,11 @@ inline int64_t long_chunk_max(int64_t w) { return int64_t(kChunkThreads) * long_
 // spans at most three 4096-element chunks.  On MI355X (n = 2^28 float32),
 // 2048 / 4096: w = 8193 1.17 / 1.20 ms, 10000 0.88 / 1.04, 20000 0.88 /
 // 0.77, 65536 0.87 / 0.77, 131072 0.91 / 0.78, 2^20 1.26 / 0.89.
-inline int long1_col_v(int64_t w) {
+// 8-byte data always takes chunks of 2048 (16 KiB, as 4096 of 4-byte data;
+// 4096 of them need 268 VGPRs: one workgroup per CU).
+inline int long1_col_v(int64_t w, size_t elem) {
   if (const int v = long_col_v_override()) return v;
-  return (w + kChunkMax - 1) / kChunkMax <= 3 ? kColVShort : kChunkV;
+  return elem == 8 || (w + kChunkMax - 1) / kChunkMax <= 3 ? kColVShort : kChunkV;
 }
 
 __host__ __device__ inline int64_t batch_tiles(int path, int64_t n, int64_t w, int64_t run) {
@@ -200,7 +202,7 @@ hipError_t launch_long(int dtype, const JobArgs& a, void* agg, hipStream_t st);
 // long1_records(n, w) chunks) and reads its siblings'; needs the stream's
 // control words (epoch) and a cooperative launch (hipErrorNotSupported when
 // a column group does not fit on the device).
-int64_t long1_records(int64_t n, int64_t w);
+int64_t long1_records(int dtype, int64_t n, int64_t w);
 hipError_t launch_long1(int dtype, const JobArgs& a, uint64_t* rec, Ctl* ctl, hipStream_t st);
 
 // Batched setup: fills S descriptors (bytes: S * series_bytes()) and the
