@@ -47,8 +47,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 WINDOWS = (16, 256, 4096, 65536)
-SERVING_RATES = (1000, 4000, 16000)
-SERVING_SECONDS = 6.0
+SERVING_RATES = "1000,4000,16000"
+SERVING_SECONDS = 30.0
+SERVING_WARMUP = 3.0
 
 
 def alg_bytes(n, w, s):
@@ -165,6 +166,10 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="measure the planner's launch parameters first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (a known-size kernel for counter calibration)")
+    ap.add_argument("--serving-rates", default=SERVING_RATES, help="request rates (per s) of the serving runs")
+    ap.add_argument("--serving-seconds", type=float, default=SERVING_SECONDS, help="measured seconds per rate")
+    ap.add_argument("--serving-warmup", type=float, default=SERVING_WARMUP, help="warm-up seconds per rate")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving sweep and print it")
     ap.add_argument("--ceiling", action="store_true",
                     help="only measure the device's copy / fill bandwidth (4 GiB buffers) and print it")
     args = ap.parse_args()
@@ -186,6 +191,9 @@ def main():
         del src, dst
     if args.ceiling:
         print(json.dumps({"ceiling": measure_ceiling(torch, dev, stream)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(args)}), flush=True)
         return
     tuning = mm.maxmin_tuning(torch.float32)
     if args.autotune:
@@ -265,6 +273,7 @@ def main():
     extras = {}
     if args.extras:
         extras = run_extras(torch, mm, synth, dev, stream, cgb)
+        extras["serving"] = run_serving(args)
 
     # CPU oracle on a bounded sample of the same workload (rank 0, N=1 only)
     import oracle
@@ -488,19 +497,27 @@ def run_extras(torch, mm, synth, dev, stream, copy_gbs):
                          "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1)}
     del xi, oo
 
-    # serving: Poisson filter requests + 1000 persistent streams, 64 GB budget
-    from paper_cs_0610046_amd.serving import serving_run
-    srv = []
-    for rate in SERVING_RATES:
-        r = serving_run(rate, SERVING_SECONDS, n_streams=1000, stream_rate=10.0)
-        srv.append(r)
-        print("[bench] serving rate=%d p50=%s p99=%s ms" % (rate, r["p50_ms"], r["p99_ms"]), file=sys.stderr,
-              flush=True)
-    out["serving"] = {"workload": "Poisson filter requests (f32/f64/i32, n log-uniform [256, 4Mi], w uniform "
-                                  "[2, 8192]) + 1000 float32 streams x 10 chunks/s of 4096 at w=512; 64 GB HBM "
-                                  "budget, 4 lanes; latency = submit to completion incl. PCIe copies",
-                      "per_rate": srv}
     return out
+
+
+def run_serving(args):
+    """Poisson filter requests + 1000 persistent streams, 64 GB budget: per
+    rate, a warm-up, then the measured seconds; and the achieved pinned
+    PCIe copy rates that bound it."""
+    from paper_cs_0610046_amd.serving import pcie_copy_rates, serving_run
+    pcie = pcie_copy_rates()
+    print("[bench] pcie %s" % pcie, file=sys.stderr, flush=True)
+    srv = []
+    for rate in [int(r) for r in args.serving_rates.split(",") if r]:
+        r = serving_run(rate, args.serving_seconds, n_streams=1000, stream_rate=10.0, warmup=args.serving_warmup)
+        srv.append(r)
+        print("[bench] serving rate=%d p50=%s p99=%s ms %.3f Gelem/s refused=%d" % (
+            rate, r["p50_ms"], r["p99_ms"], r["gelem_s"], r["refused"]), file=sys.stderr, flush=True)
+    return {"workload": "Poisson filter requests (f32/f64/i32, n log-uniform [256, 4Mi], w uniform [2, 8192]) + "
+                        "1000 float32 streams x 10 chunks/s of 4096 at w=512; 64 GB HBM budget, 4 lanes; latency = "
+                        "submit to completion incl. PCIe transfers; %.0f s measured after %.0f s of warm-up per rate"
+                        % (args.serving_seconds, args.serving_warmup),
+            "pcie": pcie, "per_rate": srv}
 
 
 if __name__ == "__main__":

@@ -285,9 +285,20 @@ int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int
  * Buffers: h_in (n or m elements) and h_max/h_min (max(0, n-w+1) elements
  * for a filter, m for a push) are HOST pointers owned by the caller and must
  * stay valid until the request is returned by maxmin_engine_poll.  Use
- * pinned memory (hipHostMalloc, torch pin_memory): pageable buffers make the
- * engine's copies synchronous.  Requests with no complete window finish at
- * once.  A request larger than the whole budget finishes with ENOMEM.
+ * pinned memory (hipHostMalloc, torch pin_memory): a batch moves the pinned
+ * (mapped) buffers under 1 MiB of all its requests with one gather kernel
+ * before its filter launches and one scatter kernel after them (a small
+ * hipMemcpyAsync costs ~10 us of copy-engine time); larger buffers take one
+ * hipMemcpyAsync each on the copy engines, and pageable buffers one
+ * synchronous hipMemcpyAsync each.  Requests with no complete
+ * window finish at once.  A request larger than the whole budget finishes
+ * with ENOMEM.
+ * Back-pressure: at most 4096 requests (environment
+ * MAXMIN_ENGINE_MAX_PENDING) wait for admission; a submit beyond that
+ * returns MAXMIN_EBUSY at once and nothing is queued (the replay call skips
+ * such a request and gives it id -1).  MAXMIN_ENGINE_COPIES=memcpy makes
+ * every buffer take hipMemcpyAsync, MAXMIN_ENGINE_COPY_MAX sets the
+ * kernel-copy size limit in bytes (experiments, tests).
  *
  * maxmin_engine_create: budget >= 1 MiB (allocated up front), 1..16 lanes,
  *   max_batch >= 1 requests per lane batch.  Errors: EINVAL, ENOMEM, EDEVICE.
@@ -307,8 +318,10 @@ int maxmin_morph_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, int
  *   or "err:K" (read at maxmin_engine_create) makes the engine's K-th batch
  *   fail before enqueuing anything, or report the look-back error word set.
  * maxmin_engine_drain: wait until every submitted request has finished.
- * maxmin_engine_stats: out8 = {submitted, finished, batches, rejected,
- *   samples processed, budget bytes in use, peak bytes in use, pending}.
+ * maxmin_engine_stats: MAXMIN_ENGINE_STATS_LEN entries = {submitted,
+ *   finished, batches, rejected (larger than the budget), samples
+ *   processed, budget bytes in use, peak bytes in use, pending, refused by
+ *   back-pressure}.
  * maxmin_engine_replay: open-loop load generator: submit request i at
  *   at_s[i] seconds after the call (kind 0 filter with dtype/n/w, kind 1
  *   push of n samples on stream sid[i]); req_ids and the submission lag
@@ -326,7 +339,8 @@ int maxmin_engine_submit_push(maxmin_engine_t* eng, int64_t stream_id, const voi
 int maxmin_engine_poll(maxmin_engine_t* eng, int64_t* ids, int64_t* n_out, double* latency_s, int* status,
                        int64_t cap, int64_t* got);
 int maxmin_engine_drain(maxmin_engine_t* eng);
-int maxmin_engine_stats(maxmin_engine_t* eng, int64_t* out8);
+#define MAXMIN_ENGINE_STATS_LEN 9
+int maxmin_engine_stats(maxmin_engine_t* eng, int64_t* out);
 int maxmin_engine_replay(maxmin_engine_t* eng, int64_t count, const double* at_s, const int* kind,
                          const int* dtype, const int64_t* n, const int64_t* w, const int64_t* sid,
                          const void* const* h_in, void* const* h_max, void* const* h_min,

@@ -456,9 +456,10 @@ class MaxMinEngine:
         _check(lib().maxmin_engine_drain(self._h))
 
     def stats(self):
-        a = (ctypes.c_int64 * 8)()
+        a = (ctypes.c_int64 * 9)()
         _check(lib().maxmin_engine_stats(self._h, a))
-        keys = ("submitted", "finished", "batches", "rejected", "samples", "bytes_in_use", "peak_bytes", "pending")
+        keys = ("submitted", "finished", "batches", "rejected", "samples", "bytes_in_use", "peak_bytes", "pending",
+                "refused")
         return dict(zip(keys, list(a)))
 
     def replay(self, at_s, kind, dtype, n, w, sid, h_in, h_max, h_min):

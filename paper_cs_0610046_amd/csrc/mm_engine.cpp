@@ -102,7 +102,31 @@ struct Req {
   int64_t off = -1, bytes = 0;  // arena block: input, then max, then min outputs
   mm::Series<float> ser{};      // what the kernels see (pointer fields only: same layout for every dtype)
   bool carry_only = false;
+  // device addresses of the host buffers when they are pinned and mapped
+  // (the batch's copy kernels move them); null: hipMemcpyAsync per buffer
+  const char* d_hin = nullptr;
+  char* d_hmax = nullptr;
+  char* d_hmin = nullptr;
 };
+
+// Device address of host memory the GPU can reach (pinned and mapped), or
+// null for pageable memory.
+const void* mapped(const void* h) {
+  if (!h) return nullptr;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, h) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory reports an error; clear it
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+  return a.devicePointer;
+}
+
+// Pieces of at most kCopyPieceMax bytes for one copy.
+void add_pieces(std::vector<mm::CopyPiece>& v, const char* src, char* dst, int64_t bytes) {
+  for (int64_t o = 0; o < bytes; o += mm::kCopyPieceMax)
+    v.push_back(mm::CopyPiece{src + o, dst + o, std::min<int64_t>(mm::kCopyPieceMax, bytes - o)});
+}
 
 struct EStream {
   int dt = 0;
@@ -142,6 +166,19 @@ struct Lane {
 struct maxmin_engine {
   Arena arena;
   int64_t max_batch = 256;
+  // Back-pressure: at most this many requests wait for admission; a submit
+  // beyond it fails with MAXMIN_EBUSY (MAXMIN_ENGINE_MAX_PENDING).
+  int64_t max_pending = 4096;
+  // Host <-> device copies of pinned, mapped buffers below copy_max bytes by
+  // the batch's copy kernels; larger ones (and pageable memory) by one
+  // hipMemcpyAsync each.  On MI355X a copy engine spends ~10 us per copy
+  // (64 KiB copies ran at 6 GB/s; one 1 GiB copy at 57 GB/s), while a kernel
+  // moves many small buffers at once; a large buffer is better left to the
+  // copy engines, which run beside the kernels.  MAXMIN_ENGINE_COPIES=memcpy
+  // sends every buffer to the copy engines, MAXMIN_ENGINE_COPY_MAX sets the
+  // size limit (experiments, tests).
+  bool copy_kernels = true;
+  int64_t copy_max = int64_t(1) << 20;
   std::vector<Lane> lanes;
   std::mutex mu;
   std::condition_variable cv_sched, cv_poll, cv_done;
@@ -154,6 +191,7 @@ struct maxmin_engine {
   int rr = 0;
   int device = 0;
   int64_t n_submitted = 0, n_done = 0, n_batches = 0, n_rejected = 0, elems_done = 0, peak_used = 0;
+  int64_t n_busy = 0;  // submissions refused by back-pressure
   int64_t in_system = 0;  // submitted and not yet collected as done
   int64_t reserved = 0;   // budget held by open streams' carries
   // Fault injection for tests (MAXMIN_ENGINE_INJECT="launch:K" or "err:K"):
@@ -278,11 +316,21 @@ void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
   const int64_t seq = ++launch_seq;
   hipError_t e = seq == inject_launch ? hipErrorLaunchFailure : hipSuccess;
   bool chunked = false;
-  // inputs
+  // inputs: pieces for the gather kernel (mapped host buffers), else copies
+  std::vector<mm::CopyPiece> pin, pout;
   for (Req* r : reqs) {
     const size_t s = esize(r->dt);
     const void* dst = r->kind == kFilter ? (const void*)r->ser.a : (const void*)r->ser.b;
-    if (e == hipSuccess && r->n > 0) e = hipMemcpyAsync((void*)dst, r->h_in, (size_t)r->n * s, hipMemcpyHostToDevice, L.st);
+    if (r->n <= 0) continue;
+    const int64_t bytes = r->n * (int64_t)s;
+    if (r->d_hin && bytes <= copy_max) add_pieces(pin, r->d_hin, (char*)dst, bytes);
+    else if (e == hipSuccess) e = hipMemcpyAsync((void*)dst, r->h_in, (size_t)bytes, hipMemcpyHostToDevice, L.st);
+  }
+  for (Req* r : reqs) {
+    const int64_t bytes = r->nout * (int64_t)esize(r->dt);
+    if (r->nout <= 0 || !r->d_hmax || bytes > copy_max) continue;
+    add_pieces(pout, (const char*)r->ser.omax, r->d_hmax, bytes);
+    add_pieces(pout, (const char*)r->ser.omin, r->d_hmin, bytes);
   }
   // descriptors, grouped by dtype
   std::vector<Group> groups;
@@ -297,52 +345,82 @@ void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
   }
   // per dtype: descriptors, then one tile-prefix array per path (tile kernel
   // of lag 1..4, chunk kernel; the path from the batched plan's size
-  // classes), built here on the host; one launch per path present
+  // classes), built here on the host; after them the copy pieces.  One
+  // upload of the whole image, then the gather kernel, one launch per path
+  // present, and (below) the scatter kernel.
   constexpr int NP = mm::kBatchNP;
+  struct GroupLaunch {
+    int dt;
+    int64_t S, run;
+    size_t pos;
+    int64_t acc[NP];
+  };
+  std::vector<GroupLaunch> gl;
   size_t total = 0;
-  for (auto& g : groups) total += g.reqs.size() * mm::series_bytes() + NP * (g.reqs.size() + 1) * sizeof(int64_t);
-  if (total > L.desc_cap) e = hipErrorOutOfMemory;  // cannot happen: admission caps the batch size
-  b->host.resize(total);
-  size_t pos = 0;
-  static const int kinds[NP] = {mm::kStratTile, mm::kStratTile2, mm::kStratTile3, mm::kStratTile4, mm::kStratChunk};
   for (auto& g : groups) {
-    if (e != hipSuccess) break;
-    const int64_t S = (int64_t)g.reqs.size();
-    const mm::BatchPlan plan = mm::batch_plan_for(g.dt);
-    const int64_t run = (int64_t)plan.run_subtiles * mm::kTileOut;
-    char* hd = b->host.data() + pos;
-    char* dd = L.desc + pos;
-    int64_t* pre = (int64_t*)(hd + S * mm::series_bytes());
-    int64_t acc[NP] = {0, 0, 0, 0, 0};
-    for (int64_t k = 0; k < S; ++k) {
-      Req* r = g.reqs[k];
-      std::memcpy(hd + k * mm::series_bytes(), &r->ser, mm::series_bytes());
-      for (int q = 0; q < NP; ++q) pre[q * (S + 1) + k] = acc[q];
-      const int path = mm::batch_path(plan, r->ser.n, r->ser.w);
-      if (path >= 0) acc[path] += mm::batch_tiles(path, r->ser.n, r->ser.w, run);
+    gl.push_back(GroupLaunch{g.dt, (int64_t)g.reqs.size(), 0, total, {0, 0, 0, 0, 0}});
+    total += g.reqs.size() * mm::series_bytes() + NP * (g.reqs.size() + 1) * sizeof(int64_t);
+  }
+  const size_t copy_at = (total + 15) & ~size_t(15);
+  total = copy_at + (pin.size() + pout.size()) * sizeof(mm::CopyPiece);
+  if (e == hipSuccess && total > L.desc_cap) {
+    // the copy pieces need room: grow the lane's buffer (batches before
+    // this one may still read the old one)
+    e = hipStreamSynchronize(L.st);
+    if (e == hipSuccess) {
+      hipFree(L.desc);
+      L.desc = nullptr;
+      L.desc_cap = 0;
+      e = hipMalloc((void**)&L.desc, 2 * total);
+      if (e == hipSuccess) L.desc_cap = 2 * total;
     }
-    for (int q = 0; q < NP; ++q) pre[q * (S + 1) + S] = acc[q];
-    const size_t gbytes = S * mm::series_bytes() + NP * (S + 1) * sizeof(int64_t);
-    e = hipMemcpyAsync(dd, hd, gbytes, hipMemcpyHostToDevice, L.st);
+  }
+  b->host.resize(total);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    GroupLaunch& G = gl[gi];
+    const int64_t S = G.S;
+    const mm::BatchPlan plan = mm::batch_plan_for(G.dt);
+    G.run = (int64_t)plan.run_subtiles * mm::kTileOut;
+    char* hd = b->host.data() + G.pos;
+    int64_t* pre = (int64_t*)(hd + S * mm::series_bytes());
+    for (int64_t k = 0; k < S; ++k) {
+      Req* r = groups[gi].reqs[k];
+      std::memcpy(hd + k * mm::series_bytes(), &r->ser, mm::series_bytes());
+      for (int q = 0; q < NP; ++q) pre[q * (S + 1) + k] = G.acc[q];
+      const int path = mm::batch_path(plan, r->ser.n, r->ser.w);
+      if (path >= 0) G.acc[path] += mm::batch_tiles(path, r->ser.n, r->ser.w, G.run);
+    }
+    for (int q = 0; q < NP; ++q) pre[q * (S + 1) + S] = G.acc[q];
+  }
+  if (!pin.empty()) std::memcpy(b->host.data() + copy_at, pin.data(), pin.size() * sizeof(mm::CopyPiece));
+  if (!pout.empty())
+    std::memcpy(b->host.data() + copy_at + pin.size() * sizeof(mm::CopyPiece), pout.data(),
+                pout.size() * sizeof(mm::CopyPiece));
+  if (e == hipSuccess && total > 0) e = hipMemcpyAsync(L.desc, b->host.data(), total, hipMemcpyHostToDevice, L.st);
+  if (e == hipSuccess)
+    e = mm::launch_copy_pieces((const mm::CopyPiece*)(L.desc + copy_at), (int64_t)pin.size(), L.st);
+  static const int kinds[NP] = {mm::kStratTile, mm::kStratTile2, mm::kStratTile3, mm::kStratTile4, mm::kStratChunk};
+  for (const GroupLaunch& G : gl) {
+    if (e != hipSuccess) break;
+    char* dd = L.desc + G.pos;
     mm::JobArgs a;
     a.mode = 1;
     a.descs = dd;
-    a.S = S;
-    a.run = run;
+    a.S = G.S;
+    a.run = G.run;
     for (int q = 0; q < NP && e == hipSuccess; ++q) {
-      if (acc[q] == 0) continue;
-      a.pre = (const int64_t*)(dd + S * mm::series_bytes()) + q * (S + 1);
+      if (G.acc[q] == 0) continue;
+      a.pre = (const int64_t*)(dd + G.S * mm::series_bytes()) + q * (G.S + 1);
       if (kinds[q] == mm::kStratChunk) {
-        if (mm::stream_lookback_state(L.st, std::min<int64_t>(acc[q], int64_t(1) << 20), &a.ring, &a.ring_lg,
+        if (mm::stream_lookback_state(L.st, std::min<int64_t>(G.acc[q], int64_t(1) << 20), &a.ring, &a.ring_lg,
                                       &a.ctl) != MAXMIN_OK) {
           e = hipErrorOutOfMemory;
           break;
         }
         chunked = true;
       }
-      e = mm::launch_1d(g.dt, kinds[q], a, (int)std::min<int64_t>(acc[q], mm::grid_cap(g.dt, kinds[q])), L.st);
+      e = mm::launch_1d(G.dt, kinds[q], a, (int)std::min<int64_t>(G.acc[q], mm::grid_cap(G.dt, kinds[q])), L.st);
     }
-    pos += gbytes;
   }
   // the chunk kernel flags a look-back wait that gave up in the lane's
   // control words: copy that word out with the batch, then clear it
@@ -370,10 +448,12 @@ void maxmin_engine::launch(int lane, std::vector<Req*>& reqs) {
       e = mm::launch_carry_only(r->dt, a, L.st);
     }
   }
-  // outputs
+  // outputs: the scatter kernel's pieces, else copies
+  if (e == hipSuccess)
+    e = mm::launch_copy_pieces((const mm::CopyPiece*)(L.desc + copy_at) + pin.size(), (int64_t)pout.size(), L.st);
   for (Req* r : reqs) {
     if (e != hipSuccess) break;
-    if (r->nout > 0) {
+    if (r->nout > 0 && (!r->d_hmax || r->nout * (int64_t)esize(r->dt) > copy_max)) {
       const size_t bytes = (size_t)r->nout * esize(r->dt);
       e = hipMemcpyAsync(r->h_max, r->ser.omax, bytes, hipMemcpyDeviceToHost, L.st);
       if (e == hipSuccess) e = hipMemcpyAsync(r->h_min, r->ser.omin, bytes, hipMemcpyDeviceToHost, L.st);
@@ -496,6 +576,15 @@ int maxmin_engine_create(int64_t hbm_budget_bytes, int n_lanes, int64_t max_batc
     return mm::set_error(MAXMIN_EINVAL, "maxmin_engine_create: budget >= 1 MiB, 1..16 lanes, max_batch >= 1");
   std::unique_ptr<maxmin_engine> e(new maxmin_engine);
   hipGetDevice(&e->device);
+  if (const char* c = getenv("MAXMIN_ENGINE_COPIES")) e->copy_kernels = strcmp(c, "memcpy") != 0;
+  if (const char* c = getenv("MAXMIN_ENGINE_COPY_MAX")) {
+    const long long v = atoll(c);
+    if (v >= 0) e->copy_max = v;
+  }
+  if (const char* c = getenv("MAXMIN_ENGINE_MAX_PENDING")) {
+    const long long v = atoll(c);
+    if (v >= 1) e->max_pending = v;
+  }
   if (const char* inj = getenv("MAXMIN_ENGINE_INJECT")) {
     long long k = 0;
     if (sscanf(inj, "launch:%lld", &k) == 1) e->inject_launch = k;
@@ -571,10 +660,26 @@ int maxmin_engine_close_stream(maxmin_engine_t* eng, int64_t stream_id) {
 }
 
 static int submit(maxmin_engine_t* eng, Req* r, int64_t* req_id) {
+  if (eng->copy_kernels && r->n > 0) {
+    // the batch's copy kernels reach pinned, mapped host buffers directly
+    const void* di = mapped(r->h_in);
+    void* dx = (void*)mapped(r->h_max);
+    void* dn = (void*)mapped(r->h_min);
+    if (di && dx && dn) {
+      r->d_hin = (const char*)di;
+      r->d_hmax = (char*)dx;
+      r->d_hmin = (char*)dn;
+    }
+  }
   std::lock_guard<std::mutex> lk(eng->mu);
   if (eng->stop) {
     delete r;
     return mm::set_error(MAXMIN_EBUSY, "maxmin_engine: shutting down");
+  }
+  if ((int64_t)eng->pending.size() >= eng->max_pending) {
+    ++eng->n_busy;
+    delete r;
+    return mm::set_error(MAXMIN_EBUSY, "maxmin_engine: admission queue full (back-pressure)");
   }
   if (r->kind == kPush) {
     auto it = eng->streams.find(r->sid);
@@ -655,6 +760,7 @@ int maxmin_engine_drain(maxmin_engine_t* eng) {
 
 int maxmin_engine_stats(maxmin_engine_t* eng, int64_t* out8) {
   if (!eng || !out8) return mm::set_error(MAXMIN_EINVAL, "maxmin_engine_stats: null argument");
+  int64_t* out = out8;  // MAXMIN_ENGINE_STATS_LEN entries
   std::lock_guard<std::mutex> lk(eng->mu);
   out8[0] = eng->n_submitted;
   out8[1] = eng->n_done;
@@ -664,6 +770,7 @@ int maxmin_engine_stats(maxmin_engine_t* eng, int64_t* out8) {
   out8[5] = eng->arena.used;
   out8[6] = eng->peak_used;
   out8[7] = (int64_t)eng->pending.size();
+  out[8] = eng->n_busy;
   return mm::set_error(MAXMIN_OK, "");
 }
 
@@ -711,7 +818,8 @@ int maxmin_engine_replay(maxmin_engine_t* eng, int64_t count, const double* at_s
     int64_t id = 0;
     int rc = kind[i] == kFilter ? maxmin_engine_submit_filter(eng, dtype[i], h_in[i], n[i], w[i], h_max[i], h_min[i], &id)
                                 : maxmin_engine_submit_push(eng, sid[i], h_in[i], n[i], h_max[i], h_min[i], &id);
-    if (rc != MAXMIN_OK) return rc;
+    if (rc == MAXMIN_EBUSY && !eng->stop) id = -1;  // refused by back-pressure: keep replaying
+    else if (rc != MAXMIN_OK) return rc;
     if (req_ids) req_ids[i] = id;
   }
   return mm::set_error(MAXMIN_OK, "");

@@ -1952,6 +1952,42 @@ template <class T> __global__ void k_tune_fill(T* a, int64_t n) {
   }
 }
 
+// Serving batches: pieces of host <-> device copies, one workgroup per
+// piece at a time, 16-byte vectors when source, destination and size allow
+// (else 4-, 2-byte or single bytes), four vectors per thread in flight so
+// that the PCIe latency of host reads is covered.
+__global__ __launch_bounds__(256) void k_copy_pieces(const CopyPiece* pieces, int64_t np) {
+  for (int64_t q = blockIdx.x; q < np; q += gridDim.x) {
+    const CopyPiece c = pieces[q];
+    const uintptr_t al = (uintptr_t)c.src | (uintptr_t)c.dst | (uintptr_t)c.bytes;
+    const int tid = threadIdx.x;
+    if ((al & 15) == 0) {
+      const u32x4* s = (const u32x4*)c.src;
+      u32x4* d = (u32x4*)c.dst;
+      const int64_t nv = c.bytes / 16;
+      for (int64_t i = tid; i < nv; i += 4 * 256) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i + u * 256 < nv) v[u] = gload(s + i + u * 256);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i + u * 256 < nv) gstore(d + i + u * 256, v[u]);
+      }
+    } else if ((al & 3) == 0) {
+      const uint32_t* s = (const uint32_t*)c.src;
+      uint32_t* d = (uint32_t*)c.dst;
+      for (int64_t i = tid; i < c.bytes / 4; i += 256) gstore(d + i, gload(s + i));
+    } else if ((al & 1) == 0) {
+      const uint16_t* s = (const uint16_t*)c.src;
+      uint16_t* d = (uint16_t*)c.dst;
+      for (int64_t i = tid; i < c.bytes / 2; i += 256) gstore(d + i, gload(s + i));
+    } else {
+      for (int64_t i = tid; i < c.bytes; i += 256) c.dst[i] = c.src[i];
+    }
+  }
+}
+
 // A push that completes no window: the new carry is simply the last
 // min(n, w-1) samples of (carry ++ chunk).
 template <class T> __global__ void k_carry_only(Series<T> s) {
@@ -2170,6 +2206,12 @@ hipError_t launch_1d(int dtype, int strategy, const JobArgs& a, int grid, hipStr
     }
     return hipGetLastError();
   });
+}
+
+hipError_t launch_copy_pieces(const CopyPiece* pieces, int64_t np, hipStream_t st) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_pieces, dim3((unsigned)std::min<int64_t>(np, 2048)), dim3(256), 0, st, pieces, np);
+  return hipGetLastError();
 }
 
 hipError_t launch_tune_fill(int dtype, void* a, int64_t n, hipStream_t st) {

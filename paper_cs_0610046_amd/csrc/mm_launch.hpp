@@ -214,6 +214,19 @@ hipError_t launch_batched_setup(int dtype, const void* d_in, const int64_t* in_o
                                 const int64_t* out_off, int64_t S, void* d_max, void* d_min, void* descs,
                                 int64_t* pre, const BatchPlan& plan, hipStream_t st);
 
+// Serving batches: many small host <-> device copies in one launch.  Each
+// piece copies `bytes` from src to dst (device addresses; host buffers must
+// be pinned and mapped, which hipHostMalloc memory is), one workgroup at a
+// time each.  A workgroup keeps 16 KiB of host reads in flight, so buffers
+// are cut into pieces of that size to spread them over workgroups.
+struct CopyPiece {
+  const char* src;
+  char* dst;
+  int64_t bytes;
+};
+constexpr int64_t kCopyPieceMax = int64_t(16) << 10;
+hipError_t launch_copy_pieces(const CopyPiece* pieces, int64_t np, hipStream_t st);
+
 // The autotuner's input: n elements of a pseudo-random pattern.
 hipError_t launch_tune_fill(int dtype, void* a, int64_t n, hipStream_t st);
 // The batched plan the planner uses for dtype (tuned or default, with the

@@ -12,7 +12,9 @@ schedule, pinned payloads, and reads back latencies.
 Payloads come from pinned pools (one 4 Mi-sample series per dtype, prefixes
 of it serve every request), and requests of one dtype share pinned output
 buffers: the benchmark measures timing, not values (the serving tests check
-values with private buffers).
+values with private buffers, up to the workload's own scale).  A request
+refused by the engine's back-pressure (its admission queue is full) counts
+as refused, not as a latency sample.
 """
 import threading
 import time
@@ -31,12 +33,49 @@ def _pinned(arr):
     return t
 
 
+def pcie_copy_rates(nbytes=1 << 30):
+    """Achieved pinned host <-> device copy bandwidth (GB/s): host to
+    device, device to host, and both at once on two streams."""
+    import torch
+    h1 = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    h2 = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    d1 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    d2 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def both():
+        with torch.cuda.stream(s1):
+            d1.copy_(h1, non_blocking=True)
+        with torch.cuda.stream(s2):
+            h2.copy_(d2, non_blocking=True)
+
+    t_h2d = timed(lambda: d1.copy_(h1, non_blocking=True))
+    t_d2h = timed(lambda: h2.copy_(d2, non_blocking=True))
+    t_both = timed(both)
+    return {"h2d_GBs": round(nbytes / t_h2d / 1e9, 1), "d2h_GBs": round(nbytes / t_d2h / 1e9, 1),
+            "both_ways_GBs": round(2 * nbytes / t_both / 1e9, 1), "bytes": nbytes}
+
+
 def serving_run(rate, duration, n_streams=1000, stream_rate=10.0, chunk=4096, stream_w=512,
-                budget=64 << 30, lanes=4, max_batch=256, seed=0):
+                budget=64 << 30, lanes=4, max_batch=256, seed=0, warmup=0.0):
+    """Replay ``warmup + duration`` seconds of the load; latency
+    percentiles and throughput count the requests that arrive after the
+    warm-up (throughput: their input samples over the time from the end of
+    the warm-up to the last completion)."""
     import torch
     rng = np.random.default_rng(np.random.SeedSequence([synth.SEED_ROOT, synth.WORKLOAD_IDS["serving"], 7, seed]))
-    reqs = synth.serving_requests(rate, duration, rng)
-    arr = synth.stream_arrivals(n_streams, stream_rate, duration, np.random.default_rng(seed + 1))
+    total_s = warmup + duration
+    reqs = synth.serving_requests(rate, total_s, rng)
+    arr = synth.stream_arrivals(n_streams, stream_rate, total_s, np.random.default_rng(seed + 1))
     pools = {np.dtype(np.float32): _pinned(synth.random_walk(MAX_N, np.float32, rng)),
              np.dtype(np.float64): _pinned(synth.random_walk(MAX_N, np.float64, rng)),
              np.dtype(np.int32): _pinned(synth.uniform_i32(MAX_N, rng))}
@@ -91,18 +130,24 @@ def serving_run(rate, duration, n_streams=1000, stream_rate=10.0, chunk=4096, st
     th.join()
     eng.drain()
     results += eng.poll()
-    wall = time.perf_counter() - t0
+    wall = time.perf_counter() - t0 - warmup
     st = eng.stats()
     for s in sids:
         eng.close_stream(s)
     eng.close()
 
-    kind_of = dict(zip(box["ids"], kind.tolist()))
-    n_of = dict(zip(box["ids"], nn.tolist()))
+    ids = box["ids"]
+    kind_of = dict(zip(ids, kind.tolist()))
+    n_of = dict(zip(ids, nn.tolist()))
+    at_of = dict(zip(ids, at_s.tolist()))
+    measured = at_s >= warmup
+    refused = int(sum(1 for i, m in zip(ids, measured) if m and i < 0))
     lat = {0: [], 1: []}
     bad = 0
     elems = 0
     for rid, no, l, status in results:
+        if at_of[rid] < warmup:
+            continue
         if status != 0:
             bad += 1
             continue
@@ -113,8 +158,9 @@ def serving_run(rate, duration, n_streams=1000, stream_rate=10.0, chunk=4096, st
         return round(float(np.percentile(v, q)) * 1e3, 4) if v else None
 
     allv = lat[0] + lat[1]
-    return {"rate_per_s": rate, "duration_s": duration, "wall_s": round(wall, 3), "requests": int((kind == 0).sum()),
-            "pushes": int((kind == 1).sum()), "failed": bad,
+    return {"rate_per_s": rate, "duration_s": duration, "warmup_s": warmup, "wall_s": round(wall, 3),
+            "requests": int(((kind == 0) & measured).sum()), "pushes": int(((kind == 1) & measured).sum()),
+            "failed": bad, "refused": refused,
             "p50_ms": pct(allv, 50), "p99_ms": pct(allv, 99),
             "filter_p50_ms": pct(lat[0], 50), "filter_p99_ms": pct(lat[0], 99),
             "push_p50_ms": pct(lat[1], 50), "push_p99_ms": pct(lat[1], 99),

@@ -91,10 +91,15 @@ def _check_mixed(eng, reqs, streams, sw=512):
         eng.close_stream(s["sid"])
 
 
+@pytest.mark.parametrize("copies", ["kernels", "memcpy"])
 @pytest.mark.parametrize("lanes", [1, 4])
-def test_engine_mixed_equals_oracle_and_alone(lanes):
+def test_engine_mixed_equals_oracle_and_alone(lanes, copies, monkeypatch):
+    """Pinned buffers move by each batch's gather / scatter kernels, or (the
+    fallback for pageable memory, forced here) one hipMemcpyAsync each."""
+    if copies == "memcpy":
+        monkeypatch.setenv("MAXMIN_ENGINE_COPIES", "memcpy")
     rng = synth.rng_for("tests", 400 + lanes)
-    note("engine mixed lanes=%d" % lanes)
+    note("engine mixed lanes=%d copies=%s" % (lanes, copies))
     eng = mm.MaxMinEngine(budget_bytes=2 << 30, lanes=lanes, max_batch=64)
     reqs, streams = _mixed(eng, rng)
     _check_mixed(eng, reqs, streams)
@@ -200,4 +205,130 @@ def test_engine_failed_batch(mode, monkeypatch):
         assert_bits_equal(mx.numpy()[:no], emx, "filter after a device error max")
         assert_bits_equal(mn.numpy()[:no], emn, "filter after a device error min")
     eng.close_stream(sid)
+    eng.close()
+
+
+@pytest.mark.timeout(900)
+def test_engine_config_scale():
+    """The serving workload's scale with private buffers: 1,000 float32
+    streams (w = 512) pushing 4096-sample chunks, mixed with filter requests
+    of float32 / float64 / int32 series of log-uniform length in [256, 4 Mi]
+    and windows in [2, 8192], submitted open-loop by the engine's replay
+    thread; every result against the oracle, and the largest filter
+    requests also against the same request run alone."""
+    import torch
+    import par_oracle
+    rng = synth.rng_for("tests", 440)
+    n_streams, pushes, chunk, sw = 1000, 3, 4096, 512
+    reqs = synth.serving_requests(40.0, 4.0, rng)  # ~160 requests of the serving mix
+    note("engine config scale: %d filter requests, %d streams x %d pushes" % (len(reqs), n_streams, pushes))
+    eng = mm.MaxMinEngine(budget_bytes=16 << 30, lanes=4, max_batch=256)
+    sids = [eng.open_stream(torch.float32, sw) for _ in range(n_streams)]
+    series = [synth.random_walk(pushes * chunk, np.float32, rng) for _ in range(n_streams)]
+    ev, keep = [], []
+    for i, (t, d, n, w) in enumerate(reqs):
+        a = synth.request_payload(d, n, 5000 + i)
+        no = max(0, n - w + 1)
+        h, mx, mn = _pin(a), _empty(no, d), _empty(no, d)
+        keep.append((a, w, h, mx, mn))
+        ev.append((t, 0, mm.dtype_code(d), n, w, 0, h.data_ptr(), mx.data_ptr(), mn.data_ptr()))
+    souts = []
+    for s in range(n_streams):
+        for p in range(pushes):
+            c = _pin(series[s][p * chunk:(p + 1) * chunk])
+            mx, mn = _empty(chunk, np.float32), _empty(chunk, np.float32)
+            souts.append((s, p, c, mx, mn))
+            # pushes of one stream in order, spread over the 4 s
+            ev.append(((p + rng.random()) * 4.0 / pushes, 1, 0, chunk, 0, sids[s], c.data_ptr(), mx.data_ptr(),
+                       mn.data_ptr()))
+    order = sorted(range(len(ev)), key=lambda j: (ev[j][0], ev[j][1]))
+    # a stream's pushes keep their order (times of push p lie in [p, p+1) * 4/3 s)
+    cols = list(zip(*[ev[j] for j in order]))
+    ids, _ = eng.replay(list(cols[0]), list(cols[1]), list(cols[2]), list(cols[3]), list(cols[4]), list(cols[5]),
+                        list(cols[6]), list(cols[7]), list(cols[8]))
+    eng.drain()
+    done = {r[0]: r for r in eng.poll()}
+    rid_of = {orig: ids[pos] for pos, orig in enumerate(order)}
+    nreq = len(reqs)
+    for i, (a, w, h, mx, mn) in enumerate(keep):
+        _, no, _, status = done[rid_of[i]]
+        assert status == 0 and no == max(0, a.size - w + 1)
+        if no == 0:
+            continue
+        emx, emn = par_oracle.wedge(a, w)
+        assert_bits_equal(mx.numpy()[:no], emx, "scale filter %d n=%d w=%d max" % (i, a.size, w))
+        assert_bits_equal(mn.numpy()[:no], emn, "scale filter %d n=%d w=%d min" % (i, a.size, w))
+    for j, (s, p, c, mx, mn) in enumerate(souts):
+        _, no, _, status = done[rid_of[nreq + j]]
+        assert status == 0
+        s_series = series[s]
+        lo = p * chunk - (sw - 1) if p > 0 else 0
+        emx, emn = oracle.wedge(s_series[lo:(p + 1) * chunk], sw)
+        assert_bits_equal(mx.numpy()[:no], emx, "scale stream %d push %d max" % (s, p))
+        assert_bits_equal(mn.numpy()[:no], emn, "scale stream %d push %d min" % (s, p))
+    # the largest requests alone, through the plain call
+    for i in sorted(range(nreq), key=lambda i: -keep[i][0].size)[:4]:
+        a, w, h, mx, mn = keep[i]
+        if a.size < w:
+            continue
+        gmx, gmn = mm.maxmin_filter(to_dev(a), w)
+        torch.cuda.synchronize()
+        no = a.size - w + 1
+        assert_bits_equal(to_host(gmx, a.dtype), mx.numpy()[:no], "alone vs mix max")
+        assert_bits_equal(to_host(gmn, a.dtype), mn.numpy()[:no], "alone vs mix min")
+    st = eng.stats()
+    assert st["submitted"] == st["finished"] and st["rejected"] == 0
+    for s in sids:
+        eng.close_stream(s)
+    eng.close()
+
+
+def test_engine_pageable_buffers_and_back_pressure(monkeypatch):
+    """Pageable (unpinned) host buffers take the copy fallback and give the
+    oracle's bits; with the admission queue capped at 4 (environment, read
+    at creation) a burst larger than the budget can admit is partly refused
+    with EBUSY, nothing refused is queued, and everything accepted finishes
+    correctly."""
+    import torch
+    rng = synth.rng_for("tests", 450)
+    eng = mm.MaxMinEngine(budget_bytes=256 << 20, lanes=2, max_batch=16)
+    a = synth.random_walk(300001, np.float64, rng)
+    mx, mn = np.zeros(a.size, np.float64), np.zeros(a.size, np.float64)  # pageable
+    note("engine pageable buffers")
+    rid = eng.submit_filter(a, 777, mx, mn)
+    eng.drain()
+    _, no, _, status = {r[0]: r for r in eng.poll()}[rid]
+    assert status == 0
+    emx, emn = oracle.wedge(a, 777)
+    assert_bits_equal(mx[:no], emx, "pageable max")
+    assert_bits_equal(mn[:no], emn, "pageable min")
+    eng.close()
+
+    monkeypatch.setenv("MAXMIN_ENGINE_MAX_PENDING", "4")
+    eng = mm.MaxMinEngine(budget_bytes=8 << 20, lanes=1, max_batch=2)
+    monkeypatch.delenv("MAXMIN_ENGINE_MAX_PENDING")
+    note("engine back-pressure")
+    # 0.8 MB in + 1.6 MB out each: three fit the budget at once; all pinned
+    # first, then submitted in a burst
+    burst = []
+    for i in range(40):
+        b = synth.random_walk(200000, np.float32, rng)
+        burst.append((b, _pin(b), _empty(b.size, np.float32), _empty(b.size, np.float32)))
+    accepted, refused = [], 0
+    for b, h, bx, bn in burst:
+        try:
+            accepted.append((eng.submit_filter(h, 100, bx, bn), b, bx, bn))
+        except mm.MaxMinError as e:
+            assert e.code == mm.MAXMIN_EBUSY
+            refused += 1
+    eng.drain()
+    done = {r[0]: r for r in eng.poll()}
+    st = eng.stats()
+    assert refused > 0 and st["refused"] == refused and st["submitted"] == len(accepted)
+    for rid, b, bx, bn in accepted:
+        _, no, _, status = done[rid]
+        assert status == 0
+        emx, emn = oracle.wedge(b, 100)
+        assert_bits_equal(bx.numpy()[:no], emx, "accepted max")
+        assert_bits_equal(bn.numpy()[:no], emn, "accepted min")
     eng.close()
