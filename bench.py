@@ -57,16 +57,15 @@ def alg_bytes(n, w, s):
 
 
 def kernel_name(strategy, w):
-    """The kernel(s) rocprofv3 names for a single-series float32 launch: the
+    """The kernel rocprofv3 names for a single-series float32 launch: the
     tile kernel (last template argument: how many sub-tiles after its start
-    a window may end), or for w > 8192 the two long-window passes (chunk
-    aggregates, then columns of chunks; 2048-element chunks where the
-    planner picks them, else 4096)."""
+    a window may end), or for w > 8192 the one-pass long-window kernel
+    (columns of 4096-element chunks; 8 elements per thread when a window
+    spans at most three chunks, else 16)."""
     if strategy == "tile":
         return "mm::k_tile<0, float, false, %d>" % (1 if w <= 2048 else (w + 2047) // 2048)
     k = (w + 4095) // 4096
-    v = 8 if w <= 65536 and (k * 4096 == w or k <= 3) else 16
-    return "mm::k_chunk_agg<float, %d> + mm::k_chunk_col<float, %d>" % (v, v)
+    return "mm::k_chunk_col1<float, %d>" % (8 if k <= 3 else 16)
 
 
 # Sources whose change invalidates counter-derived traffic figures.
@@ -166,7 +165,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="measure the planner's launch parameters first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (a known-size kernel for counter calibration)")
-    ap.add_argument("--serving-rates", default=SERVING_RATES, help="request rates (per s) of the serving runs")
+    ap.add_argument("--serving-rates", default=SERVING_RATES,
+                    help="request rates (per s) of the serving runs, comma-separated ('none': no serving runs)")
     ap.add_argument("--serving-seconds", type=float, default=SERVING_SECONDS, help="measured seconds per rate")
     ap.add_argument("--serving-warmup", type=float, default=SERVING_WARMUP, help="warm-up seconds per rate")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving sweep and print it")
@@ -273,7 +273,8 @@ def main():
     extras = {}
     if args.extras:
         extras = run_extras(torch, mm, synth, dev, stream, cgb)
-        extras["serving"] = run_serving(args)
+        if args.serving_rates != "none":
+            extras["serving"] = run_serving(args)
 
     # CPU oracle on a bounded sample of the same workload (rank 0, N=1 only)
     import oracle
