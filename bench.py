@@ -75,11 +75,17 @@ TRAFFIC_FILE = "profiles/hbm_traffic_f32_walk_n2p28.md"
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources' code: comments and whitespace are dropped,
+    so editing documentation does not void the counter figures."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

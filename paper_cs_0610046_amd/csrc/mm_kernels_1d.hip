@@ -10,26 +10,36 @@
 // maximum (likewise for the minimum).  With B = w this is the classical
 // form (no middle term).  All of it is selection: results are exact.
 //
-// * Tile strategy (w <= 1024).  One workgroup produces kTileOut windows from
-//   the kTileOut + w - 1 inputs they need, staged in LDS.  B is the largest
-//   power of two <= min(w, 512), so w <= 2B and at most one whole block lies
-//   strictly inside any window.  Threads own 8 consecutive positions; a
-//   block spans B/8 lanes of one wavefront, so SUF/PRE need only in-thread
-//   scans plus a lane-group scan (ds_bpermute shuffles) -- no workgroup-wide
-//   scan and no segmented scan.  PRE is written to LDS and read back at
-//   offset w-1 by the thread that owns the window's start.
+// * Tile strategy (k_tile, w <= 8192).  A persistent workgroup of 256
+//   threads streams through a run of consecutive sub-tiles of 2048 windows,
+//   each thread holding 8 consecutive positions in registers (16-byte loads,
+//   the next sub-tile's loads in flight while the current one is scanned).
+//   For w <= 2048, B is the largest power of two <= min(w, 1024), so w <= 2B
+//   and at most one whole block lies inside a window; in-thread scans plus
+//   DPP lane-group scans give PRE/SUF (B = 1024 folds two wavefronts through
+//   LDS).  PRE goes to an LDS ring of two sub-tiles, SUF stays in registers,
+//   and the windows starting in the previous sub-tile are stored with
+//   shifted 16-byte stores.  LAG = 2..4 (w <= 4096 / 6144 / 8192) take whole
+//   sub-tiles as blocks and keep the SUF of LAG sub-tiles in registers.
+//   Job kinds: one series (optionally two segments: a stream's carry plus
+//   its chunk), described series of a batch, rows of a 2-D image.
 //
-// * Chunk strategy (any w, used for w > 1024).  Blocks of exactly w inputs
-//   aligned at the series start, cut into K chunks of C <= 2048.  The
-//   workgroup that owns input chunk (b, k) emits every window that ENDS in
-//   that chunk (the paper's zero-latency view, Section 1, applied to
-//   chunks): PRE comes from its own chunk plus the aggregates of chunks
-//   (b, 0..k-1); SUF comes from re-reading chunk (b-1, k) (w inputs back,
-//   still in cache) plus the aggregates of chunks (b-1, k+1..K-1).  Each
-//   workgroup publishes its chunk's aggregate as soon as it has loaded it,
-//   and only ever waits on the K-1 chunks handed out just before it
-//   (in-order tickets), so progress is guaranteed and every input is read
-//   from HBM once.
+// * Chunk strategy (k_chunk, batched windows past the tile kernel, forced
+//   for tests).  Blocks of exactly w inputs aligned at the series start, cut
+//   into K chunks of C <= 4096.  The workgroup that owns input chunk (b, k)
+//   emits every window that ENDS in it (the zero-latency view of Section 1
+//   applied to chunks): PRE from its own chunk plus the aggregates of chunks
+//   (b, 0..k-1), SUF from re-reading chunk (b-1, k) plus the aggregates of
+//   chunks (b-1, k+1..K-1).  Chunks are taken by in-order tickets; each
+//   publishes its aggregate before waiting, and waits only on the K-1
+//   chunks ticketed just before it, so every wait ends.
+//
+// * Long windows of one series (w > 8192).  k_chunk_col1: one pass, a
+//   column of chunks per workgroup (K sibling columns run together under a
+//   cooperative launch and exchange chunk records); k_chunk_agg +
+//   k_chunk_col: the two-pass form (aggregates, then columns) for devices
+//   where the cooperative grid does not fit; k_chunk with look-back on
+//   request.
 #include <type_traits>
 
 #include "mm_launch.hpp"
