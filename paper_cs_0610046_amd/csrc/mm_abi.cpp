@@ -537,6 +537,21 @@ int maxmin_argfilter(int dtype, const void* d_in, int64_t n, int64_t w, void* d_
   if (!aligned(d_in, s) || !aligned(d_max, s) || !aligned(d_min, s) || !aligned(d_argmax, 8) || !aligned(d_argmin, 8))
     return fail(MAXMIN_EINVAL, "maxmin_argfilter: pointer not aligned to the element size");
   hipStream_t st = (hipStream_t)stream;
+  // 4096 < w <= 2^29: per-chunk aggregates, then columns of chunks (the
+  // input read twice, each output written once).  MAXMIN_ARG_CHUNK=0 keeps
+  // the level-array paths below (tests).
+  {
+    const char* eh = getenv("MAXMIN_ARG_CHUNK");
+    if (w > mm::kTileMaxW2 && w <= (int64_t(1) << 29) && !(eh && !strcmp(eh, "0"))) {
+      Workspace* ws = nullptr;
+      int r = get_ws(st, &ws);
+      if (r) return r;
+      if ((r = ensure_tmp(ws, mm::arg_chunk_scratch(dtype, n, w)))) return r;
+      hipError_t e = mm::launch_arg_chunks(dtype, d_in, n, w, ws->tmp, d_max, d_argmax, d_min, d_argmin, st);
+      if (e != hipSuccess) return hip_fail(e, "maxmin_argfilter (chunks)");
+      return ok();
+    }
+  }
   // 2 x 4096 < w <= 31 x 4096: the tile kernel at q = floor(w / F), F =
   // ceil(w / 4096), then one running window of F rows of q level entries
   // (each entry read once).  On MI355X (n = 2^28 float32) it beat the

@@ -252,6 +252,12 @@ hipError_t launch_env_short(int dtype, const void* in, const int64_t* off, const
 // 2..kArgColsMaxF rows of q entries plus, if Fq < w, the entry at j+w-q
 // ((F+1)q >= w required).  hipErrorInvalidValue outside those limits.
 constexpr int64_t kArgColsMaxF = 31;
+// Arg filter for 4096 < w <= 2^29 in two passes over chunks (per-chunk
+// leftmost max / min, then columns of chunks): scratch of
+// arg_chunk_scratch(dtype, n, w) bytes, 16-byte aligned.
+size_t arg_chunk_scratch(int dtype, int64_t n, int64_t w);
+hipError_t launch_arg_chunks(int dtype, const void* d_in, int64_t n, int64_t w, void* scratch, void* ox, int64_t* jx,
+                             void* on, int64_t* jn, hipStream_t st);
 hipError_t launch_arg_cols(int dtype, const void* vx, const int64_t* ix, const void* vn, const int64_t* in,
                            int64_t nlv, int64_t q, int64_t w, int64_t nout, void* ox, int64_t* jx, void* on,
                            int64_t* jn, hipStream_t st);

@@ -1,8 +1,9 @@
 """GPU parity of the arg max/min filter (leftmost locations) against the
 oracle: values bit-exact against the wedge, locations exact against the
 linear-time deque (itself pinned to the definition), over every dtype, tie-
-heavy and smooth inputs, windows served by the tile kernel and by doubling
-steps, ragged sizes and misaligned buffers; at n = 2^28, sampled windows
+heavy and smooth inputs, windows served by the tile kernel, by columns of
+chunks, by rows of level entries and by combine steps, ragged sizes and
+misaligned buffers; at n = 2^28, sampled windows
 against the definition plus whole-array properties."""
 import numpy as np
 import pytest
@@ -55,10 +56,14 @@ def _check(a, w, what, off=(0, 0, 0, 0, 0)):
     assert bad.size == 0, "%s argmin: %d mismatches, first at %d: got %d want %d" % (what, bad.size, bad[0], gin[bad[0]], ein[bad[0]])
 
 
-@pytest.fixture(params=["rows", "chain"])
+@pytest.fixture(params=["chunks", "rows", "chain"])
 def argpath(request, monkeypatch):
-    """Windows over 4096: one running window over rows of level entries, or
-    (MAXMIN_ARG_CHAIN=1) the combine steps, which also serve w > 31 x 4096."""
+    """Windows over 4096: per-chunk aggregates then columns of chunks (the
+    default), or (MAXMIN_ARG_CHUNK=0) one running window over rows of level
+    entries, or (also MAXMIN_ARG_CHAIN=1) the combine steps, which also
+    serve w > 31 x 4096."""
+    if request.param != "chunks":
+        monkeypatch.setenv("MAXMIN_ARG_CHUNK", "0")
     if request.param == "chain":
         monkeypatch.setenv("MAXMIN_ARG_CHAIN", "1")
     return request.param
@@ -99,7 +104,7 @@ def test_argfilter_misaligned():
 
 @pytest.mark.timeout(600)
 def test_argfilter_full_size_sampled():
-    """n = 2^28 float32 walk at windows 256, 4096 and 65536 (a combine step):
+    """n = 2^28 float32 walk at windows 256, 4096 and 65536 (columns of chunks):
     sampled windows against the definition (numpy's first-occurrence argmax
     over the window), every location inside its window, and the values at
     the locations equal to the max/min outputs."""

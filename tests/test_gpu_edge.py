@@ -146,14 +146,16 @@ def test_edge_values_2d(dt, monkeypatch):
 @pytest.mark.parametrize("dt", DTS, ids=IDS)
 def test_edge_values_arg(dt, monkeypatch):
     """Leftmost locations among runs of equal extremes: the tile kernel with
-    locations (both lags), the running window over level rows, and the
-    combine steps."""
+    locations (both lags), columns of chunks, the running window over level
+    rows, and the combine steps."""
     import torch
     a = _series(150001, dt, 906)
     x = to_dev(a)
-    for w, chain in ((1, "0"), (5, "0"), (700, "0"), (3000, "0"), (10000, "0"), (10000, "1"), (70000, "1")):
+    for w, chain, chunk in ((1, "0", "1"), (5, "0", "1"), (700, "0", "1"), (3000, "0", "1"), (10000, "0", "1"),
+                            (70000, "0", "1"), (10000, "0", "0"), (10000, "1", "0"), (70000, "1", "0")):
         monkeypatch.setenv("MAXMIN_ARG_CHAIN", chain)
-        note("edge arg dt=%s w=%d chain=%s" % (np.dtype(dt).name, w, chain))
+        monkeypatch.setenv("MAXMIN_ARG_CHUNK", chunk)
+        note("edge arg dt=%s w=%d chain=%s chunk=%s" % (np.dtype(dt).name, w, chain, chunk))
         gmx, gmn, gix, gin = mm.maxmin_argfilter(x, w)
         torch.cuda.synchronize()
         emx, emn = oracle.wedge(a, w)
