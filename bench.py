@@ -452,7 +452,7 @@ def run_extras(torch, mm, synth, dev, stream, copy_gbs):
         res[str(w)] = {"ms": round(ms, 4), "gelem_s": round(xa.numel() / (ms * 1e-3) / 1e9, 2),
                        "pct_hbm": round(100 * ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
                        "path": "tile with locations" if w <= 4096 else
-                       ("tile + combine step" if w <= 8192 else "tile + running window over level rows")}
+                       "chunk aggregates + columns of chunks with locations"}
         del outs
     out["argfilter"] = {"workload": "n=2^28 float32 walk; max, min and their leftmost int64 locations "
                                     "(algorithmic bytes: 4 read + 24 written per window)", "per_window": res}
