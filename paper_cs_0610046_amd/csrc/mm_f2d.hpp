@@ -383,13 +383,15 @@ __device__ __forceinline__ void f2_wave_sync() {
 // positions < 64 V + wc - 1 are read); rx / rn get max / min over
 // [p, p + wc - 1] for the lane's positions p.  Blocks of Bh = 2^lgBh <= 16 V
 // positions, mh = max(1, Bh / V) lanes each (lig = lane & (mh - 1)); at
-// most KM whole blocks inside a window (KM = 1 when wc <= 16 V, as then
-// Bh > wc / 2; else 4).  hpx / hpn: this wavefront's LDS row
+// most kmax whole blocks inside a window.  KM > 0: read a fixed KM of them
+// (KM = 1 when wc <= 16 V, as then Bh > wc / 2; else 4), clamped, so that
+// all the reads of a row go out together; KM = 0: a loop to kmax (fewer
+// registers live: the one-output kernels and the envelopes keep it).  hpx / hpn: this wavefront's LDS row
 // buffer of lds_len<T>(128 V) elements (only the side WX / WN is used).
 // The caller orders the buffer's next reuse (f2_wave_sync).
 template <class T, int V, int KM, bool WX, bool WN>
 __device__ __forceinline__ void f2_row_filter(const T (&x)[V], const T (&h)[V], int wc, int lgBh, int mh, int lig,
-                                              T* hpx, T* hpn, T (&rx)[V], T (&rn)[V]) {
+                                              int kmax, T* hpx, T* hpn, T (&rx)[V], T (&rn)[V]) {
   constexpr int W = 64 * V;
   const int lane = threadIdx.x & 63;
   const int Bh = 1 << lgBh;
@@ -458,10 +460,9 @@ __device__ __forceinline__ void f2_row_filter(const T (&x)[V], const T (&h)[V], 
     if constexpr (WX) rx[i] = hmax(sx[i], hpx[lds_idx<T>(e)]);
     if constexpr (WN) rn[i] = hmin(sn[i], hpn[lds_idx<T>(e)]);
     // whole blocks b1+1 .. inside the window; past the last one the
-    // index clamps to e, whose PRE is already taken (a fixed count, so
-    // that all the reads of a row are issued together)
+    // index clamps to e, whose PRE is already taken
 #pragma unroll
-    for (int k = 1; k <= KM; ++k) {
+    for (int k = 1; k <= (KM > 0 ? KM : kmax); ++k) {
       const int mi = min((((b1 + k + 1) << lgBh) - 1), e);
       if constexpr (WX) rx[i] = hmax(rx[i], hpx[lds_idx<T>(mi)]);
       if constexpr (WN) rn[i] = hmin(rn[i], hpn[lds_idx<T>(mi)]);
@@ -502,6 +503,10 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<typename F2Store<T>::S> a) {
   const int Bh = 1 << lgBh;
   const int mh = Bh > V ? Bh / V : 1;  // lanes per block, <= 16
   const int lig = lane & (mh - 1);
+  const int kmax = max(0, (wc + Bh - 2) / Bh - 1);
+  // the column suffix of the window's first row read before the row work
+  // (both outputs; with one output the registers it holds cost more)
+  constexpr bool EARLY = OUT == 3;
   // down the columns: blocks of B rows (wr <= 2B)
   constexpr int lgB = B == 1 ? 0 : (B == 2 ? 1 : (B == 4 ? 2 : (B == 8 ? 3 : (B == 16 ? 4 : 5))));
 
@@ -557,10 +562,12 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<typename F2Store<T>::S> a) {
         const int j = t - wr + 1, bj = j >> lgB, bt = t >> lgB;
         const int js = j & (RB - 1);
         T sjx[V], sjn[V];
+        if constexpr (EARLY) {
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          if constexpr (WX) sjx[i] = ringx[(js * V + i) * 64 + lane];
-          if constexpr (WN) sjn[i] = ringn[(js * V + i) * 64 + lane];
+          for (int i = 0; i < V; ++i) {
+            sjx[i] = ringx[(js * V + i) * 64 + lane];
+            sjn[i] = ringn[(js * V + i) * 64 + lane];
+          }
         }
         T rx[V], rn[V];  // the row-filtered values of this lane's columns
         if constexpr (COLS) {
@@ -570,7 +577,7 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<typename F2Store<T>::S> a) {
           // ---- along the row
           T x[V], h[V];
           f2_row_take<T, V>(buf[d], x, h);
-          f2_row_filter<T, V, KM, WX, WN>(x, h, wc, lgBh, mh, lig, hpx, hpn, rx, rn);
+          f2_row_filter<T, V, KM, WX, WN>(x, h, wc, lgBh, mh, lig, kmax, hpx, hpn, rx, rn);
           f2_wave_sync();  // the row buffer is rewritten by the next row
           // the next loads into this slot of the row queue
           if (t + D < NR) f2_row_issue<T, V, VIN>(a, r0 + t + D, c0, buf[d]);
@@ -590,6 +597,15 @@ __global__ __launch_bounds__(64) void k_f2d(F2dArgs<typename F2Store<T>::S> a) {
           T ox[V], on[V];
 #pragma unroll
           for (int i = 0; i < V; ++i) {
+            if constexpr (!EARLY) {
+              if (use_s) {
+                if constexpr (WX) sjx[i] = ringx[(js * V + i) * 64 + lane];
+                if constexpr (WN) sjn[i] = ringn[(js * V + i) * 64 + lane];
+              } else {
+                sjx[i] = Px[i];
+                sjn[i] = Pn[i];
+              }
+            }
             const T mx = hmax(Px[i], sjx[i]), mn = hmin(Pn[i], sjn[i]);
             ox[i] = use_s ? mx : Px[i];
             on[i] = use_s ? mn : Pn[i];
@@ -626,20 +642,23 @@ template <class T, int V> bool f2_vin(const F2dArgs<typename F2Store<T>::S>& a) 
 
 template <class T, int B, int V, bool COLS, int OUT>
 hipError_t f2d_go(const F2dArgs<typename F2Store<T>::S>& a, int64_t grid, hipStream_t st) {
-  if constexpr (!COLS) {
-    if (a.wc > 16 * V) {  // up to four whole row blocks inside a window
-      if (f2_vin<T, V>(a))
-        hipLaunchKernelGGL((k_f2d<T, B, V, 4, true, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
-      else
-        hipLaunchKernelGGL((k_f2d<T, B, V, 4, false, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
-      return hipGetLastError();
-    }
+  const bool vin = f2_vin<T, V>(a);
+  auto go = [&](auto km) {
+    constexpr int KM = decltype(km)::value;
+    if (vin) hipLaunchKernelGGL((k_f2d<T, B, V, KM, true, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_f2d<T, B, V, KM, false, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
+    return hipGetLastError();
+  };
+  if constexpr (COLS) {
+    return go(std::integral_constant<int, 1>());  // no row work
+  } else if constexpr (OUT != 3) {
+    return go(std::integral_constant<int, 0>());  // one output: the loop over whole row blocks
+  } else {
+    // both outputs: a fixed count of whole row blocks, up to four when a
+    // window is wider than 16 V columns
+    if (a.wc > 16 * V) return go(std::integral_constant<int, 4>());
+    return go(std::integral_constant<int, 1>());
   }
-  if (f2_vin<T, V>(a))
-    hipLaunchKernelGGL((k_f2d<T, B, V, 1, true, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_f2d<T, B, V, 1, false, COLS, OUT>), dim3((unsigned)grid), dim3(64), 0, st, a);
-  return hipGetLastError();
 }
 
 // Shared launcher: COLS = column-only mode (in, in2: the row-filtered max

@@ -28,6 +28,7 @@ __global__ __launch_bounds__(256) void k_env_short(const T* in, const int64_t* o
   const int Bh = 1 << lgBh;
   const int mh = Bh > V ? Bh / V : 1;
   const int lig = lane & (mh - 1);
+  const int kmax = max(0, (wc + Bh - 2) / Bh - 1);
   const T* a = in + s0;
   T* const bx = hpx[wv];  // the row buffer also stages loads and stores
   T* const bn = hpn[wv];
@@ -54,9 +55,7 @@ __global__ __launch_bounds__(256) void k_env_short(const T* in, const int64_t* o
       h[i] = bx[lds_idx<T>(W + lane * V + i)];  // past np: unused positions
     }
     f2_wave_sync();
-    // up to one whole row block inside a window when wc <= 16 V, else four
-    if (wc > 16 * V) f2_row_filter<T, V, 4, true, true>(x, h, wc, lgBh, mh, lig, bx, bn, rx, rn);
-    else f2_row_filter<T, V, 1, true, true>(x, h, wc, lgBh, mh, lig, bx, bn, rx, rn);
+    f2_row_filter<T, V, 0, true, true>(x, h, wc, lgBh, mh, lig, kmax, bx, bn, rx, rn);
     f2_wave_sync();
 #pragma unroll
     for (int i = 0; i < V; ++i) {
