@@ -161,6 +161,18 @@ int maxmin_out_offsets(const int64_t* h_in_offsets, const int64_t* h_windows, in
  *   waiting for the handle's last push to finish (an event recorded on that
  *   push's stream; no device-wide synchronisation).  NULL is accepted.
  * maxmin_stream_samples: samples pushed so far (t), or -1 for NULL.
+ * maxmin_stream_export: the stream's whole state, (t, its last min(t, w-1)
+ *   samples): waits for the handle's last push, copies the samples (oldest
+ *   first) into h_carry (host memory, capacity >= min(t, w-1) elements, may
+ *   be NULL when that is 0) and t into *h_t.  The handle is unchanged.
+ *   Errors: EINVAL (null handle or h_t, null h_carry with samples to copy),
+ *   EDEVICE.
+ * maxmin_stream_import: a new handle on the current device that continues
+ *   from an exported state (dtype and w as the stream was created with):
+ *   pushing to it emits exactly what pushing to the original would have
+ *   (checkpoint / resume, or moving a stream to another device or process).
+ *   The caller keeps h_carry.  Errors: EINVAL (w < 1, t < 0, bad dtype,
+ *   null out, null h_carry with samples to copy), ENOMEM, EDEVICE.
  */
 typedef struct maxmin_stream maxmin_stream_t;
 int maxmin_stream_create(int dtype, int64_t w, maxmin_stream_t** out);
@@ -168,6 +180,8 @@ int maxmin_stream_push(maxmin_stream_t* st, const void* d_chunk, int64_t m, void
                        void* d_min, int64_t* h_n_out, void* stream);
 int maxmin_stream_destroy(maxmin_stream_t* st);
 int64_t maxmin_stream_samples(const maxmin_stream_t* st);
+int maxmin_stream_export(const maxmin_stream_t* st, void* h_carry, int64_t* h_t);
+int maxmin_stream_import(int dtype, int64_t w, int64_t t, const void* h_carry, maxmin_stream_t** out);
 
 /*
  * maxmin_filter_2d -- the 1-D filter applied to rows, then to columns

@@ -204,7 +204,13 @@ def argdeque(a, w):
 
 class Stream:
     """The wedge kept across pushes: push(chunk) returns the windows that the
-    chunk completes (zero stream latency)."""
+    chunk completes (zero stream latency, Section 1).
+
+    export() gives the stream's state as (t, the last min(t, w-1) samples):
+    every later window lies within the samples from t-w+1 on, so that is all
+    a continuation needs.  Stream.resume(dtype, w, t, carry) rebuilds a wedge
+    from it by pushing the carried samples, which complete no window (fewer
+    than w of them), and counts samples from t."""
 
     def __init__(self, dtype, w):
         self.dtype = np.dtype(dtype)
@@ -213,6 +219,19 @@ class Stream:
         self._h = self._lib.oracle_stream_create(DTYPES[self.dtype], self.w)
         if not self._h:
             raise ValueError("oracle_stream_create failed")
+        self._t = 0
+        self._carry = np.empty(0, self.dtype)
+
+    @classmethod
+    def resume(cls, dtype, w, t, carry):
+        st = cls(dtype, w)
+        carry = np.ascontiguousarray(carry, dtype=st.dtype)
+        if carry.size != max(0, min(int(t), st.w - 1)):
+            raise ValueError("carry must hold min(t, w-1) samples")
+        mx, _ = st.push(carry)
+        assert mx.size == 0
+        st._t = int(t)
+        return st
 
     def push(self, chunk):
         chunk = np.ascontiguousarray(chunk, dtype=self.dtype)
@@ -220,7 +239,13 @@ class Stream:
         mx = np.empty(cap, self.dtype)
         mn = np.empty(cap, self.dtype)
         k = self._lib.oracle_stream_push(self._h, _ptr(chunk), chunk.size, _ptr(mx), _ptr(mn))
+        self._t += chunk.size
+        keep = min(self._t, self.w - 1)
+        self._carry = np.concatenate([self._carry, chunk])[len(self._carry) + chunk.size - keep:].copy()
         return mx[:k].copy(), mn[:k].copy()
+
+    def export(self):
+        return self._t, self._carry.copy()
 
     def stats(self):
         t, c, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -50,6 +50,8 @@ def lib():
         L.maxmin_stream_destroy.argtypes = [vp]
         L.maxmin_stream_samples.argtypes = [vp]
         L.maxmin_stream_samples.restype = i64
+        L.maxmin_stream_export.argtypes = [vp, vp, i64p]
+        L.maxmin_stream_import.argtypes = [ci, i64, i64, vp, ctypes.POINTER(vp)]
         L.maxmin_filter_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, vp, vp, i64, vp]
         L.maxmin_morph_2d.argtypes = [ci, vp, i64, i64, i64, i64, i64, ci, vp, i64, vp]
         L.maxmin_autotune.argtypes = [ci, i64, vp]
@@ -80,7 +82,7 @@ def lib():
         L.maxmin_last_error.restype = ctypes.c_char_p
         L.maxmin_version.restype = ctypes.c_char_p
         for f in ("maxmin_filter", "maxmin_filter_noalloc", "maxmin_argfilter", "maxmin_filter_batched", "maxmin_out_offsets", "maxmin_stream_create",
-                  "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_filter_2d", "maxmin_morph_2d",
+                  "maxmin_stream_push", "maxmin_stream_destroy", "maxmin_stream_export", "maxmin_stream_import", "maxmin_filter_2d", "maxmin_morph_2d",
                   "maxmin_envelope", "maxmin_envelope_batched", "maxmin_autotune", "maxmin_tuning",
                   "maxmin_set_strategy",
                   "maxmin_plan", "maxmin_plan_2d", "maxmin_check_stream"):
@@ -107,6 +109,11 @@ def dtype_code(dtype):
         return _TORCH_CODES[dtype]
     d = np.dtype(dtype)
     return {np.dtype(np.float32): 0, np.dtype(np.float64): 1, np.dtype(np.int32): 2, np.dtype(np.uint16): 3}[d]
+
+
+def _np_dtype(dtype):
+    """The numpy dtype of a torch or numpy dtype."""
+    return [np.float32, np.float64, np.int32, np.uint16][dtype_code(dtype)]
 
 
 def _stream(stream):
@@ -217,14 +224,26 @@ def maxmin_filter_batched(packed, in_offsets, windows, out_offsets, out_max=None
 
 
 class MaxMinStream:
-    """maxmin_stream_create / push / destroy: zero-latency chunked filtering."""
+    """maxmin_stream_create / push / destroy: zero-latency chunked filtering;
+    export / import of the stream's state (t, last min(t, w-1) samples)."""
 
-    def __init__(self, dtype, w):
+    def __init__(self, dtype, w, _handle=None):
         self.dtype = dtype
         self.w = int(w)
+        if _handle is not None:
+            self._h = _handle
+            return
         h = ctypes.c_void_p()
         _check(lib().maxmin_stream_create(dtype_code(dtype), self.w, ctypes.byref(h)))
         self._h = h
+
+    def export(self):
+        """(t, carry): carry a host numpy array of the last min(t, w-1) samples."""
+        t = ctypes.c_int64(0)
+        c = max(0, min(self.samples, self.w - 1))
+        carry = np.empty(c, dtype=_np_dtype(self.dtype))
+        _check(lib().maxmin_stream_export(self._h, carry.ctypes.data if c else None, ctypes.byref(t)))
+        return t.value, carry
 
     def push(self, chunk, out_max=None, out_min=None, stream=None, which="both"):
         import torch
@@ -259,6 +278,17 @@ class MaxMinStream:
 
 def maxmin_stream_create(dtype, w):
     return MaxMinStream(dtype, w)
+
+
+def maxmin_stream_import(dtype, w, t, carry):
+    """A stream that continues from an exported state (t, carry)."""
+    carry = np.ascontiguousarray(carry, dtype=_np_dtype(dtype))
+    if carry.size != max(0, min(int(t), int(w) - 1)):
+        raise ValueError("carry must hold min(t, w-1) samples")
+    h = ctypes.c_void_p()
+    _check(lib().maxmin_stream_import(dtype_code(dtype), int(w), int(t), carry.ctypes.data if carry.size else None,
+                                      ctypes.byref(h)))
+    return MaxMinStream(dtype, w, _handle=h)
 
 
 def _check_img(img):

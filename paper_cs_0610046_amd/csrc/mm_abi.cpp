@@ -818,6 +818,43 @@ int maxmin_stream_push(maxmin_stream_t* st, const void* d_chunk, int64_t m, void
 
 int64_t maxmin_stream_samples(const maxmin_stream_t* st) { return st ? st->t : -1; }
 
+// A stream's whole state is (t, its last min(t, w-1) samples): export copies
+// it out after the handle's last push has finished; import builds a handle
+// that continues from it (on the current device).
+int maxmin_stream_export(const maxmin_stream_t* st, void* h_carry, int64_t* h_t) {
+  if (!st || !h_t) return fail(MAXMIN_EINVAL, "maxmin_stream_export: null handle or h_t");
+  const int64_t c = std::min(st->t, st->w - 1);
+  if (c > 0 && !h_carry) return fail(MAXMIN_EINVAL, "maxmin_stream_export: null h_carry");
+  hipError_t e = hipEventSynchronize(st->last);
+  if (e == hipSuccess && c > 0) e = hipMemcpy(h_carry, st->carry[st->cur], (size_t)c * dsize(st->dt), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "maxmin_stream_export");
+  *h_t = st->t;
+  return ok();
+}
+
+int maxmin_stream_import(int dtype, int64_t w, int64_t t, const void* h_carry, maxmin_stream_t** out) {
+  if (!out) return fail(MAXMIN_EINVAL, "maxmin_stream_import: null out");
+  *out = nullptr;
+  if (!dsize(dtype)) return fail(MAXMIN_EINVAL, "maxmin_stream_import: unknown dtype %d", dtype);
+  if (w < 1) return fail(MAXMIN_EINVAL, "maxmin_stream_import: window w=%lld < 1", (long long)w);
+  if (t < 0) return fail(MAXMIN_EINVAL, "maxmin_stream_import: t=%lld < 0", (long long)t);
+  const int64_t c = std::min(t, w - 1);
+  if (c > 0 && !h_carry) return fail(MAXMIN_EINVAL, "maxmin_stream_import: null h_carry");
+  maxmin_stream_t* st = nullptr;
+  int r = maxmin_stream_create(dtype, w, &st);
+  if (r) return r;
+  if (c > 0) {
+    const hipError_t e = hipMemcpy(st->carry[st->cur], h_carry, (size_t)c * dsize(dtype), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      maxmin_stream_destroy(st);
+      return hip_fail(e, "maxmin_stream_import");
+    }
+  }
+  st->t = t;
+  *out = st;
+  return ok();
+}
+
 int maxmin_stream_destroy(maxmin_stream_t* st) {
   if (!st) return ok();
   // the carries may still be read or written by the last push: wait for it

@@ -81,6 +81,13 @@ def test_argument_errors_without_gpu(lib):
     assert lib.maxmin_stream_push(None, None, 4, None, None, None, None) == binding.MAXMIN_EINVAL
     assert lib.maxmin_stream_destroy(None) == binding.MAXMIN_OK
     assert lib.maxmin_stream_samples(None) == -1
+    t = ctypes.c_int64(0)
+    assert lib.maxmin_stream_export(None, None, ctypes.byref(t)) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_stream_import(0, 8, -1, None, ctypes.byref(h)) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_stream_import(0, 0, 3, None, ctypes.byref(h)) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_stream_import(7, 8, 3, None, ctypes.byref(h)) == binding.MAXMIN_EINVAL
+    assert lib.maxmin_stream_import(0, 8, 3, None, ctypes.byref(h)) == binding.MAXMIN_EINVAL  # 3 samples, no carry
+    assert lib.maxmin_stream_import(0, 8, 3, None, None) == binding.MAXMIN_EINVAL
 
 
 def test_tuning_table_and_autotune_arguments(lib):

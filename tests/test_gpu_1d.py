@@ -257,6 +257,43 @@ def test_stream_chunks_equal_one_shot(w, monkeypatch):
         mm.maxmin_check_stream()
 
 
+@pytest.mark.parametrize("w", [1, 5, 64, 3000, 20000])
+def test_stream_export_import(w):
+    """Checkpoint and resume: at random points the GPU stream's state (t and
+    its last min(t, w-1) samples) is exported, compared bit for bit with the
+    oracle's, and a new handle is imported from it (alternately from the
+    GPU's export and from the oracle's); the outputs continue exactly as
+    the oracle stream's."""
+    import torch
+    rng = synth.rng_for("tests", 110)
+    for dt in DTS:
+        a = gen(60000, dt, rng, "walk")
+        st = mm.maxmin_stream_create(to_dev(a[:1]).dtype, w)
+        ost = oracle.Stream(dt, w)
+        pos, k = 0, 0
+        while pos < a.size:
+            m = int(rng.integers(0, 2 * w + 40))
+            chunk = a[pos:pos + m]
+            note("stream export/import dt=%s w=%d pos=%d m=%d" % (np.dtype(dt).name, w, pos, m))
+            gmx, gmn = st.push(to_dev(chunk))
+            omx, omn = ost.push(chunk)
+            torch.cuda.synchronize()
+            assert_bits_equal(to_host(gmx, dt), omx, "stream max pos=%d" % pos)
+            assert_bits_equal(to_host(gmn, dt), omn, "stream min pos=%d" % pos)
+            pos += len(chunk)
+            if rng.random() < 0.3:
+                gt, gc = st.export()
+                ot, oc = ost.export()
+                assert gt == ot == pos
+                assert_bits_equal(gc, oc, "exported carry at t=%d" % pos)
+                st.close()
+                k += 1
+                st = mm.maxmin_stream_import(to_dev(a[:1]).dtype, w, *((gt, gc) if k % 2 else (ot, oc)))
+                assert st.samples == pos
+        st.close()
+        mm.maxmin_check_stream()
+
+
 def test_batched_mixed():
     import torch
     rng = synth.rng_for("tests", 107)
