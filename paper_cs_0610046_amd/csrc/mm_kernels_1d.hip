@@ -146,12 +146,50 @@ __device__ __forceinline__ Series<T> job_series(const Job<T>& j, int64_t t, int6
 // is read from memory once; only a run's last sub-tile overlaps the next run.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <class T> struct TileLds {
+template <class T, bool COMPACT = false> struct TileLds {
   T pm[lds_len<T>(2 * kTileOut)];  // PRE (max) ring, indexed by position mod 2*kTileOut
   T pn[lds_len<T>(2 * kTileOut)];  // PRE (min) ring
   T wt[4][kTileThreads / 64];      // wavefront totals (blocks of two or four wavefronts)
   T st[2][8];                      // LAG >= 3: sub-tile totals, indexed by sub-tile mod 8
 };
+// With locations at LAG 1: a PRE entry's location lies at most 2047
+// positions before its own (inside its block), so the rings keep the value
+// and that distance as 16 bits, 6 bytes an entry for 4-byte data instead of
+// 8 (f32: 50.7 instead of 66.6 KiB, three workgroups per CU instead of two;
+// MI355X, n = 2^28: w = 1024 2.12 -> 1.94 ms, 2048 2.26 -> 1.99; at LAG 2,
+// held to two workgroups by its registers, it was 2% slower).
+template <class T> struct TileLds<Loc<T>, true> {
+  T pmv[lds_len<T>(2 * kTileOut)];
+  T pnv[lds_len<T>(2 * kTileOut)];
+  uint16_t pmd[lds_len<uint16_t>(2 * kTileOut)];
+  uint16_t pnd[lds_len<uint16_t>(2 * kTileOut)];
+  Loc<T> wt[4][kTileThreads / 64];
+  Loc<T> st[2][8];
+};
+// ring access: slot (ring index) of position pos (relative to the run start)
+template <class T> __device__ __forceinline__ void ring_put(TileLds<T, false>& sm, int slot, int, T x, T n) {
+  sm.pm[lds_idx<T>(slot)] = x;
+  sm.pn[lds_idx<T>(slot)] = n;
+}
+template <class T>
+__device__ __forceinline__ void ring_put(TileLds<Loc<T>, true>& sm, int slot, int pos, Loc<T> x, Loc<T> n) {
+  sm.pmv[lds_idx<T>(slot)] = x.v;
+  sm.pnv[lds_idx<T>(slot)] = n.v;
+  sm.pmd[lds_idx<uint16_t>(slot)] = (uint16_t)(pos - x.i);
+  sm.pnd[lds_idx<uint16_t>(slot)] = (uint16_t)(pos - n.i);
+}
+template <class T> __device__ __forceinline__ T ring_x(const TileLds<T, false>& sm, int slot, int) {
+  return sm.pm[lds_idx<T>(slot)];
+}
+template <class T> __device__ __forceinline__ T ring_n(const TileLds<T, false>& sm, int slot, int) {
+  return sm.pn[lds_idx<T>(slot)];
+}
+template <class T> __device__ __forceinline__ Loc<T> ring_x(const TileLds<Loc<T>, true>& sm, int slot, int pos) {
+  return Loc<T>{sm.pmv[lds_idx<T>(slot)], pos - (int)sm.pmd[lds_idx<uint16_t>(slot)]};
+}
+template <class T> __device__ __forceinline__ Loc<T> ring_n(const TileLds<Loc<T>, true>& sm, int slot, int pos) {
+  return Loc<T>{sm.pnv[lds_idx<T>(slot)], pos - (int)sm.pnd[lds_idx<uint16_t>(slot)]};
+}
 
 // Series and outputs need not be 16-byte aligned (a packed batch puts
 // series at arbitrary element offsets).  A wavefront covers 64 * 8
@@ -346,7 +384,8 @@ __device__ __forceinline__ void run_store(T* om, T* on, bool ovec, int d, int64_
 // or several (L >= 3: the totals of the last 8 sub-tiles, kept in LDS).
 template <class T, bool ARG, int LAG>
 __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t R1,
-                                         TileLds<typename ElemOf<T, ARG>::type>& sm, int64_t* amax,
+                                         TileLds<typename ElemOf<T, ARG>::type, ARG && LAG == 1>& sm,
+                                         int64_t* amax,
                                          int64_t* amin) {
   typedef typename ElemOf<T, ARG>::type E;
   E* const et = nullptr;  // selects elem()'s overload
@@ -521,8 +560,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
       const int slot = pr0 & (RING - 1);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        sm.pm[lds_idx<E>(slot + i)] = px[i];
-        sm.pn[lds_idx<E>(slot + i)] = pn[i];
+        ring_put(sm, slot + i, pr0 + i, px[i], pn[i]);
       }
       if constexpr (LAG >= 3) {
         if (tid == NT - 1) {  // PRE at the sub-tile's last position: its total
@@ -560,17 +598,17 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const int q = qr0 + i, e = q + w - 1;
-        E rx = hmax(hx[LAG - 1][i], sm.pm[lds_idx<E>(e & (RING - 1))]);
-        E rn = hmin(hn[LAG - 1][i], sm.pn[lds_idx<E>(e & (RING - 1))]);
+        E rx = hmax(hx[LAG - 1][i], ring_x(sm, e & (RING - 1), e));
+        E rn = hmin(hn[LAG - 1][i], ring_n(sm, e & (RING - 1), e));
         const int b1 = q >> lgB, b2 = e >> lgB;
         if constexpr (LAG >= 3) {
           const bool last = b2 == b1 + LAG;  // ends in P_k
           rx = hmax(rx, last ? mx0 : mx1);
           rn = hmin(rn, last ? mn0 : mn1);
         } else if (b2 >= b1 + 2) {
-          const int mi = (((b1 + 2) << lgB) - 1) & (RING - 1);
-          rx = hmax(rx, sm.pm[lds_idx<E>(mi)]);
-          rn = hmin(rn, sm.pn[lds_idx<E>(mi)]);
+          const int mp = ((b1 + 2) << lgB) - 1;  // the whole block's last position
+          rx = hmax(rx, ring_x(sm, mp & (RING - 1), mp));
+          rn = hmin(rn, ring_n(sm, mp & (RING - 1), mp));
         }
         ox[i] = rx;
         on[i] = rn;
@@ -618,7 +656,7 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
 // w-1 halo; on MI355X this beat the XCD-contiguous schedule by ~2%).
 template <int MODE, class T, bool ARG = false, int LAG = 1>
 __global__ __launch_bounds__(kTileThreads) void k_tile(Job<T> job) {
-  __shared__ TileLds<typename ElemOf<T, ARG>::type> sm;
+  __shared__ TileLds<typename ElemOf<T, ARG>::type, ARG && LAG == 1> sm;
   const int64_t nruns = job_tiles<MODE>(job);
   if constexpr (MODE == kJobDescs) {
     // Described series: workgroup g takes the g-th of gridDim.x equal,
