@@ -146,28 +146,44 @@ int plan_strategy(int dt, int64_t n, int64_t w) {
   return MAXMIN_STRATEGY_CHUNK;
 }
 
-// The fused 2-D pass serves the windows it fits up to 15 rows (4- and
-// 8-byte data, both outputs) or 31 rows (16-bit data, or one output: its
-// LDS ring is then half the size); past those its one column per lane and
-// the 32- or 64-row LDS ring lose to rows-then-columns.  On MI355X
-// (8192^2): float32 w = 24 / 31 / 63 fused 0.54 / 0.54 / 1.11 ms against
-// 0.50 / 0.50 / 0.65 ms; uint16 w = 31 / 63 fused 0.38 / 0.77 ms against
-// 0.40 / 0.60 ms; float32 max-only w = 31 / 63 fused 0.31 / 0.56 ms
-// against 0.36 / 0.52 ms.  MAXMIN_2D_FUSED=0 / =1 force either path where
-// both apply (experiments and tests).
+// The fused 2-D pass serves the windows it fits up to 15 rows (23 for
+// 16-bit data with both outputs); past those its one column per lane and
+// LDS ring of 2B rows lose to rows-then-columns with the streaming ring
+// column pass.  On MI355X (8192^2, square windows, ms per call, fused /
+// rows-then-columns): float32 w = 15 0.30 / 0.46, 16 0.45 / 0.42, 31 0.50
+// / 0.45, 63 0.90 / 0.51; float32 max-only w = 15 0.17 / 0.26, 16 0.27 /
+// 0.25, 31 0.29 / 0.27; uint16 w = 20 0.30 / 0.33, 24 0.31 / 0.31, 31 0.32
+// / 0.30; uint16 max-only w = 15 0.11 / 0.22, 16 0.21 / 0.20.
+// MAXMIN_2D_FUSED=0 / =1 force either path where both apply (experiments
+// and tests).
 bool fused_2d(int dtype, int64_t w_rows, int64_t w_cols, bool one_output) {
   if (!mm::f2d_eligible(dtype, w_rows, w_cols)) return false;
   const char* e = getenv("MAXMIN_2D_FUSED");
   if (e && !strcmp(e, "0")) return false;
   if (e && !strcmp(e, "1")) return true;
-  return w_rows < (dsize(dtype) == 2 || one_output ? 32 : 16);
+  return w_rows < (dsize(dtype) == 2 && !one_output ? 24 : 16);
 }
 // Column pass of rows-then-columns: the fused kernel's column filter alone
 // (streaming down bands) for windows under 16 rows and for 16-bit data,
 // else blocks of w_rows rows (on MI355X, 8192^2 float32, w = 31 / 63: 0.31
 // / 0.47 ms against 0.50 / 0.87 ms for the streaming filter; uint16 w =
 // 63: 0.80 against 0.45 ms the other way).
-bool stream_cols_2d(int dtype, int64_t w_rows) { return w_rows < 16 || (dsize(dtype) == 2 && w_rows <= 64); }
+// Which column pass: 0 blocks of w_rows rows (launch_cols), 1 the fused
+// kernel's streaming column filter, 2 the LDS-ring streaming pass.  From 16
+// rows on the ring (MI355X, 8192^2, whole call: float32 w = 16 / 31 / 63
+// 0.42 / 0.45 / 0.51 ms against 0.48 / 0.49 / 0.50 streaming and 0.51 /
+// 0.49 / 0.53 blocks; uint16 0.29 / 0.30 / 0.32 against 0.30 / 0.32 /
+// 0.42 streaming); below it the streaming filter (its ring of 2B rows is
+// small there).  MAXMIN_COLS_PASS=block / stream / ring forces one where it
+// applies (experiments, tests).
+int cols_pass_2d(int dtype, int64_t w_rows) {
+  const char* e = getenv("MAXMIN_COLS_PASS");
+  if (e && !strcmp(e, "block")) return 0;
+  if (e && !strcmp(e, "stream")) return 1;
+  if (e && !strcmp(e, "ring")) return 2;
+  if (dsize(dtype) != 8 && w_rows >= 16 && w_rows <= 64) return 2;
+  return w_rows < 16 || (dsize(dtype) == 2 && w_rows <= 64) ? 1 : 0;
+}
 
 // Long windows of a single series (more than one chunk per block): the
 // one-pass column kernel; the look-back chunk kernel only when
@@ -895,7 +911,9 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   Workspace* ws = nullptr;
   int r = get_ws(st, &ws);
   if (r) return r;
-  const size_t img = (size_t)rows * (size_t)oc * s;
+  // intermediate rows padded to 64 elements: every row starts 256-byte aligned
+  const int64_t ldt = (oc + 63) / 64 * 64;
+  const size_t img = (size_t)rows * (size_t)ldt * s;
   const bool big = w_rows > mm::cols_max_window(dtype);
   const size_t scr = big ? (size_t)mm::cols_scratch_elems(rows, oc, w_rows) * s : 0;
   if ((r = ensure_tmp(ws, 2 * img + scr))) return r;
@@ -911,7 +929,7 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   a.w = w_cols;
   a.omax = tmax;
   a.omin = tmin;
-  a.ld_out = oc;
+  a.ld_out = ldt;
   const int strat = plan_strategy(dtype, cols, w_cols);
   hipError_t e;
   if (strat == MAXMIN_STRATEGY_TILE) {
@@ -936,11 +954,16 @@ int maxmin_filter_2d(int dtype, const void* d_in, int64_t rows, int64_t cols, in
   }
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (rows)");
   // column pass
-  e = stream_cols_2d(dtype, w_rows)
-          ? mm::launch_f2d_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, 0, st)
-          : hipErrorNotSupported;
+  const int cp = cols_pass_2d(dtype, w_rows);
+  const char* ecb = getenv("MAXMIN_COLS_BAND");
+  e = hipErrorNotSupported;
+  if (cp == 2)
+    e = mm::launch_cols_ring(dtype, tmax, tmin, ldt, rows, oc, w_rows, d_max, d_min, ld_out, ecb ? atoll(ecb) : 0,
+                             st);
+  if (cp == 1 || (cp == 2 && e == hipErrorNotSupported && w_rows < 16))
+    e = mm::launch_f2d_cols(dtype, tmax, tmin, ldt, rows, oc, w_rows, d_max, d_min, ld_out, 0, st);
   if (e == hipErrorNotSupported)
-    e = mm::launch_cols(dtype, tmax, tmin, oc, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
+    e = mm::launch_cols(dtype, tmax, tmin, ldt, rows, oc, w_rows, d_max, d_min, ld_out, gscr, st);
   if (e != hipSuccess) return hip_fail(e, "maxmin_filter_2d (columns)");
   return ok();
 }

@@ -279,6 +279,15 @@ int set_error(int code, const char* msg);
 hipError_t launch_cols(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
                        int64_t wr, void* d_max, void* d_min, int64_t ld_out, void* gscratch, hipStream_t st);
 int64_t cols_max_window(int dtype);
+// Column pass streaming down bands of output rows with each column's block
+// in an LDS ring (float32 / int32 / uint16; each lane takes 1, 2 or 4
+// 32-bit words of a row, so ld_t must be a multiple of the words' elements
+// and the images aligned to the access), w_rows <= 64, else
+// hipErrorNotSupported.  Either image may be null for a one-output call.
+// band_rows <= 0: the launcher picks the band height.
+hipError_t launch_cols_ring(int dtype, const void* tmax, const void* tmin, int64_t ld_t, int64_t rows, int64_t oc,
+                            int64_t wr, void* d_max, void* d_min, int64_t ld_out, int64_t band_rows,
+                            hipStream_t st);
 
 // Fused 2-D filter (one pass, no intermediate images) for w_rows <= 64 and
 // w_cols <= 64 * V + 1 (V = 4, 4, 4, 2, 1, 1 for column blocks 1..32);

@@ -116,8 +116,8 @@ def test_out_offsets_matches_oracle(lib):
 
 def test_planner_2d(lib, monkeypatch):
     """The 2-D path choice: the fused pass for the windows it fits (w_rows
-    <= 64, w_cols <= 64 V + 1) up to w_rows 15 (4- and 8-byte data) or 31
-    (16-bit data)."""
+    <= 64, w_cols <= 64 V + 1) up to w_rows 15, or 23 for 16-bit data with
+    both outputs; rows then columns beyond."""
     monkeypatch.delenv("MAXMIN_2D_FUSED", raising=False)
     F, RC = binding.PLAN_2D_FUSED, binding.PLAN_2D_ROWS_COLS
     for dt in (np.float32, np.float64, np.int32, np.uint16):
@@ -125,13 +125,14 @@ def test_planner_2d(lib, monkeypatch):
         assert binding.maxmin_plan_2d(dt, 7, 257) == F and binding.maxmin_plan_2d(dt, 7, 258) == RC
         assert binding.maxmin_plan_2d(dt, 15, 129) == F and binding.maxmin_plan_2d(dt, 15, 130) == RC
         big = F if dt == np.uint16 else RC
-        assert binding.maxmin_plan_2d(dt, 16, 65) == big and binding.maxmin_plan_2d(dt, 31, 66) == RC
-        assert binding.maxmin_plan_2d(dt, 31, 65) == big
+        assert binding.maxmin_plan_2d(dt, 16, 65) == big and binding.maxmin_plan_2d(dt, 16, 66) == RC
+        assert binding.maxmin_plan_2d(dt, 23, 65) == big and binding.maxmin_plan_2d(dt, 24, 65) == RC
+        assert binding.maxmin_plan_2d(dt, 31, 65) == RC
         assert binding.maxmin_plan_2d(dt, 32, 3) == RC and binding.maxmin_plan_2d(dt, 63, 63) == RC
         assert binding.maxmin_plan_2d(dt, 65, 1) == RC
-        # one output: the fused pass up to w_rows 31 for every type
-        assert binding.maxmin_plan_2d(dt, 31, 65, outputs=1) == F
-        assert binding.maxmin_plan_2d(dt, 32, 3, outputs=1) == RC
+        # one output: the fused pass up to w_rows 15 for every type
+        assert binding.maxmin_plan_2d(dt, 15, 65, outputs=1) == F
+        assert binding.maxmin_plan_2d(dt, 16, 3, outputs=1) == RC
     monkeypatch.setenv("MAXMIN_2D_FUSED", "1")
     assert binding.maxmin_plan_2d(np.float32, 63, 63) == F
     monkeypatch.setenv("MAXMIN_2D_FUSED", "0")

@@ -122,3 +122,54 @@ def test_2d_fused_edges(dt, monkeypatch):
     omx, omn = oracle.filter2d(a, 5, 9)
     assert_bits_equal(to_host(gmx, dt), omx, "single pixel max")
     assert_bits_equal(to_host(gmn, dt), omn, "single pixel min")
+
+
+@pytest.mark.parametrize("cpass", ["block", "stream", "ring", "ring-v1d8", "ring-v1d16", "ring-v2d8", "ring-v2d16",
+                                   "ring-v4d8"])
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32, np.uint16], ids=lambda d: np.dtype(d).name)
+def test_2d_column_passes(dt, cpass, monkeypatch):
+    """Rows then columns with each column pass forced (blocks of w_rows rows,
+    the fused kernel's streaming column filter, the streaming LDS ring with
+    its default and every instantiated lane width V and prefetch depth D):
+    every window size class up to 64 rows, odd and even output widths (lane
+    groups cut by the image edge), bands of one and of several blocks (every
+    band re-reads w_rows - 1 rows), offset outputs (stores that cannot be
+    widened) and one-output calls."""
+    import torch
+    rng = synth.rng_for("tests", 203)
+    monkeypatch.setenv("MAXMIN_2D_FUSED", "0")
+    monkeypatch.setenv("MAXMIN_COLS_PASS", cpass.split("-")[0])
+    if "-" in cpass:
+        v, d = cpass.split("-")[1][1:].split("d")
+        monkeypatch.setenv("MAXMIN_COLS_V", v)
+        monkeypatch.setenv("MAXMIN_COLS_D", d)
+    for wr in (1, 2, 15, 16, 17, 31, 33, 48, 49, 63, 64):
+        wc = int(rng.integers(1, 9))
+        rows = wr + int(rng.integers(0, 300))
+        cols = wc + int(rng.integers(0, 400))
+        a = _image(rows, cols, dt, rng)
+        for band in (None, "1", str(3 * wr)):
+            if band is None:
+                monkeypatch.delenv("MAXMIN_COLS_BAND", raising=False)
+            else:
+                monkeypatch.setenv("MAXMIN_COLS_BAND", band)
+            note("2d cols=%s dt=%s %dx%d w=%dx%d band=%s" % (cpass, np.dtype(dt).name, rows, cols, wr, wc, band))
+            gmx, gmn = mm.maxmin_filter_2d(to_dev(a), wr, wc)
+            omx, omn = oracle.filter2d(a, wr, wc)
+            assert_bits_equal(to_host(gmx, dt), omx, "cols %s max %dx%d" % (cpass, wr, wc))
+            assert_bits_equal(to_host(gmn, dt), omn, "cols %s min %dx%d" % (cpass, wr, wc))
+        monkeypatch.delenv("MAXMIN_COLS_BAND", raising=False)
+        orow, ocol = rows - wr + 1, cols - wc + 1
+        x = to_dev(a)
+        bx = torch.zeros((orow, ocol + 5), dtype=x.dtype, device="cuda")
+        bn = torch.zeros((orow, ocol + 5), dtype=x.dtype, device="cuda")
+        note("2d cols=%s dt=%s offset outputs w=%d" % (cpass, np.dtype(dt).name, wr))
+        mm.maxmin_filter_2d(x, wr, wc, bx[:, 1:ocol + 1], bn[:, 3:ocol + 3])
+        gx, _ = mm.maxmin_filter_2d(x, wr, wc, which="max")
+        _, gn = mm.maxmin_filter_2d(x, wr, wc, which="min")
+        torch.cuda.synchronize()
+        omx, omn = oracle.filter2d(a, wr, wc)
+        assert_bits_equal(to_host(bx[:, 1:ocol + 1], dt), omx, "offset max")
+        assert_bits_equal(to_host(bn[:, 3:ocol + 3], dt), omn, "offset min")
+        assert_bits_equal(to_host(gx, dt), omx, "max-only")
+        assert_bits_equal(to_host(gn, dt), omn, "min-only")
