@@ -646,8 +646,12 @@ __device__ __forceinline__ void run_body(const Series<T>& s, int64_t R0, int64_t
     }
     // Let this sub-tile's stores complete before the next one's loads are
     // issued: on MI355X 3-6% faster per launch than leaving them in flight
-    // with the next loads at one or two sub-tiles of lag, even at four.
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt untouched
+    // with the next loads at one or two sub-tiles of lag, even at four.  The
+    // arg filter writes three times the bytes per output (values and 8-byte
+    // locations) and gains from leaving them in flight while the next
+    // sub-tile's scans run (n = 2^28 float32: w = 4096 2.33 -> 2.11 ms, w <=
+    // 2048 1-2%); its next wait for loads then covers them.
+    if constexpr (!ARG) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt untouched
     lds_barrier();  // ring slots of P_{k-1} may now be reused by P_{k+1}
   }
 }
