@@ -371,8 +371,8 @@ int maxmin_plan(int dtype, int64_t n, int64_t w);
 
 /* Path maxmin_filter_2d takes for (dtype, w_rows, w_cols) with `outputs`
  * (2: max and min; 1: one of them null): MAXMIN_2D_FUSED (one pass, no
- * intermediate images: w_rows < 16, or w_rows < 32 for 16-bit data or one
- * output, and w_cols <= 64 V + 1 with V = 4 for w_rows < 8, 2 for
+ * intermediate images: w_rows < 16, or w_rows < 24 for 16-bit data with
+ * both outputs, and w_cols <= 64 V + 1 with V = 4 for w_rows < 8, 2 for
  * w_rows < 16, else 1) or MAXMIN_2D_ROWS_COLS (rows, then columns through
  * two library-owned intermediate images).  EINVAL for an unknown dtype, a
  * window < 1 or outputs not 1 or 2.  Host only. */
