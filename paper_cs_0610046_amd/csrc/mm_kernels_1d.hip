@@ -897,6 +897,28 @@ __device__ __forceinline__ void chunk_store(T* out, const T* buf, int rs, int le
   for (int r = a0 + nv * EV + tid; r < len; r += NT) gstore(out + r, buf[lds_idx<T>(r)]);
 }
 
+// chunk_store of max(buf[r], c) (MAXF) or min(buf[r], c): a staged chunk's
+// outputs with one more aggregate folded in as they leave LDS.
+template <class T, bool MAXF>
+__device__ __forceinline__ void chunk_store_fold(T* out, const T* buf, int rs, int len, T c) {
+  constexpr int NT = kChunkThreads, EV = 16 / (int)sizeof(T);
+  const int tid = threadIdx.x;
+  auto f = [&](int r) { return MAXF ? hmax(buf[lds_idx<T>(r)], c) : hmin(buf[lds_idx<T>(r)], c); };
+  int a0 = rs;
+  while (a0 < len && (((uintptr_t)(out + a0)) & 15) != 0) ++a0;  // uniform, < EV steps
+  for (int r = rs + tid; r < a0; r += NT) gstore(out + r, f(r));
+  const int nv = (len - a0) / EV;
+  for (int v = tid; v < nv; v += NT) {
+    T e[EV];
+#pragma unroll
+    for (int k = 0; k < EV; ++k) e[k] = f(a0 + v * EV + k);
+    u32x4 u;
+    __builtin_memcpy(&u, e, 16);
+    gstore_nt((u32x4*)(out + a0 + v * EV), u);
+  }
+  for (int r = a0 + nv * EV + tid; r < len; r += NT) gstore(out + r, f(r));
+}
+
 // counter: where the next ticket comes from.
 template <class T>
 __device__ void chunk_body(const Series<T>& s, int64_t t, int64_t gbase, const FlagRing& ring, uint32_t ep,
@@ -1232,11 +1254,21 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col(Series<T> s, const 
 // earlier.  A range's first block needs the block before it, which the
 // previous range reaches only at its end, so every workgroup also publishes
 // its column's chunk of that block (loaded anyway; the previous range later
-// publishes the same values).  A workgroup publishes before it waits, and
-// waits only on records of its own step or earlier, so with every workgroup
-// resident (the launch is cooperative) every wait ends; one that outlasts
-// the spin limit sets the error word instead of hanging.
-template <class T, int V>
+// publishes the same values).  DEFER: a chunk's outputs wait one step for
+// the siblings' records -- at step b a workgroup stages everything it knows
+// of chunk b's windows (its own prefix and the previous chunk's suffix,
+// across the workgroup) in LDS, and only after publishing chunk b+1 fetches
+// the records chunk b needs and stores its outputs with them folded in, so
+// the K workgroups of a range do not wait on each other's current step.
+// On MI355X (n = 2^28) that pays where K is large (float32 w = 262144, K =
+// 64: 0.81 -> 0.75 ms; 2^20, K = 256: 0.89 -> 0.79; float64 w = 65536, K =
+// 32: 1.51 -> 1.40) and costs 3-6% where it is small (float32 w = 8193 ..
+// 65536, K <= 16: 0.78 -> 0.81 ms at 65536), so it is taken from K = 32.  A
+// workgroup publishes before it waits, and waits only on records of its own
+// step or earlier, so with every workgroup resident (the launch is
+// cooperative) every wait ends; one that outlasts the spin limit sets the
+// error word instead of hanging.
+template <class T, int V, bool DEFER>
 __global__ __launch_bounds__(kChunkThreads) void k_chunk_col1(Series<T> s, uint64_t* rec, Ctl* ctl) {
   constexpr int64_t CM = int64_t(kChunkThreads) * V;
   constexpr int NW = kChunkThreads / 64;
@@ -1284,6 +1316,40 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col1(Series<T> s, uint6
       }
     }
   }
+  // Stores of chunk (b, k), staged in LDS a step earlier: fold in the
+  // siblings' chunks (b, 0..k-1) on the PRE side and (b-1, k+1..K-1) on the
+  // SUF side, then write the outputs; the LDS is free again on return.
+  auto flush = [&](int64_t b) {
+    const int64_t p0 = b * w + k * C;
+    const int len = (int)min((int64_t)lenfull, n - p0);
+    if (tid < 64) {
+      T ax = Lim<T>::lo(), an = Lim<T>::hi();
+      for (int64_t j = tid; j < K; j += 64) {
+        if (j < k || (j > k && b >= 1)) {
+          T mx, mn;
+          fetch<T>(rec + 4 * ((j < k ? b : b - 1) * K + j), ep, mx, mn, ctl);
+          ax = hmax(ax, mx);
+          an = hmin(an, mn);
+        }
+      }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        ax = hmax(ax, (T)__shfl_xor(ax, d, 64));
+        an = hmin(an, (T)__shfl_xor(an, d, 64));
+      }
+      if (tid == 0) {
+        sm.dep[0] = ax;
+        sm.dep[1] = an;
+      }
+    }
+    __syncthreads();
+    const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
+    if (s.omax) chunk_store_fold<T, true>(s.omax + (p0 - w + 1), sm.xs, rs, len, sm.dep[0]);
+    if (s.omin) chunk_store_fold<T, false>(s.omin + (p0 - w + 1), sm.hs, rs, len, sm.dep[1]);
+    __syncthreads();
+  };
+  bool pend = false;  // a chunk's outputs wait in LDS for its siblings' records
+  int64_t pb = 0;     // its block
   if (b0 < b1 && b0 * w + k * C < n) {
     col_load<T, V>(s, b0 * w + k * C, (int)min((int64_t)lenfull, n - (b0 * w + k * C)), cur);
     for (int64_t b = b0; b < b1; ++b) {
@@ -1334,52 +1400,72 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col1(Series<T> s, uint6
       wg_scan2<T>(epx, epn, esx, esn, tx, tn, sm);
       // this chunk's max and min, for the siblings' windows
       if (tid == 0) publish<T>(rec + 4 * (b * K + k), tx, tn, ep);
-      if (has_out && tid < 64) {
-        // (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
-        T prx = Lim<T>::lo(), prn = Lim<T>::hi(), sux = Lim<T>::lo(), sun = Lim<T>::hi();
-        for (int64_t j = tid; j < K; j += 64) {
-          if (j < k) {
-            T mx, mn;
-            fetch<T>(rec + 4 * (b * K + j), ep, mx, mn, ctl);
-            prx = hmax(prx, mx);
-            prn = hmin(prn, mn);
-          } else if (j > k && b >= 1) {
-            T mx, mn;
-            fetch<T>(rec + 4 * ((b - 1) * K + j), ep, mx, mn, ctl);
-            sux = hmax(sux, mx);
-            sun = hmin(sun, mn);
+      if constexpr (DEFER) {
+        // the previous step's chunk: its siblings' records, then its outputs
+        if (pend) flush(pb);
+        if (has_out) {
+          // what this workgroup knows of the windows ending in this chunk:
+          // the previous chunk's suffix and this one's prefix, each completed
+          // across the workgroup (the siblings' chunks come a step later)
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            const int r = r0 + i;
+            if (r < len) {
+              sm.xs[lds_idx<T>(r)] = hmax(hmax(bx[i], esx), hmax(epx, ax[i]));
+              sm.hs[lds_idx<T>(r)] = hmin(hmin(bn[i], esn), hmin(epn, an[i]));
+            }
           }
         }
+        pend = has_out;
+        pb = b;
+      } else {
+        if (has_out && tid < 64) {
+          // (b, 0..k-1) feed PRE, (b-1, k+1..K-1) feed SUF
+          T prx = Lim<T>::lo(), prn = Lim<T>::hi(), sux = Lim<T>::lo(), sun = Lim<T>::hi();
+          for (int64_t j = tid; j < K; j += 64) {
+            if (j < k) {
+              T mx, mn;
+              fetch<T>(rec + 4 * (b * K + j), ep, mx, mn, ctl);
+              prx = hmax(prx, mx);
+              prn = hmin(prn, mn);
+            } else if (j > k && b >= 1) {
+              T mx, mn;
+              fetch<T>(rec + 4 * ((b - 1) * K + j), ep, mx, mn, ctl);
+              sux = hmax(sux, mx);
+              sun = hmin(sun, mn);
+            }
+          }
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          prx = hmax(prx, (T)__shfl_xor(prx, d, 64));
-          prn = hmin(prn, (T)__shfl_xor(prn, d, 64));
-          sux = hmax(sux, (T)__shfl_xor(sux, d, 64));
-          sun = hmin(sun, (T)__shfl_xor(sun, d, 64));
-        }
-        if (tid == 0) {
-          sm.dep[0] = prx;
-          sm.dep[1] = prn;
-          sm.dep[2] = sux;
-          sm.dep[3] = sun;
-        }
-      }
-      __syncthreads();
-      if (has_out) {
-        const T prx = hmax(sm.dep[0], epx), prn = hmin(sm.dep[1], epn);
-        const T sux = hmax(sm.dep[2], esx), sun = hmin(sm.dep[3], esn);
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          const int r = r0 + i;
-          if (r < len) {
-            sm.xs[lds_idx<T>(r)] = hmax(hmax(bx[i], sux), hmax(prx, ax[i]));
-            sm.hs[lds_idx<T>(r)] = hmin(hmin(bn[i], sun), hmin(prn, an[i]));
+          for (int d = 32; d >= 1; d >>= 1) {
+            prx = hmax(prx, (T)__shfl_xor(prx, d, 64));
+            prn = hmin(prn, (T)__shfl_xor(prn, d, 64));
+            sux = hmax(sux, (T)__shfl_xor(sux, d, 64));
+            sun = hmin(sun, (T)__shfl_xor(sun, d, 64));
+          }
+          if (tid == 0) {
+            sm.dep[0] = prx;
+            sm.dep[1] = prn;
+            sm.dep[2] = sux;
+            sm.dep[3] = sun;
           }
         }
         __syncthreads();
-        const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
-        if (s.omax) chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
-        if (s.omin) chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+        if (has_out) {
+          const T prx = hmax(sm.dep[0], epx), prn = hmin(sm.dep[1], epn);
+          const T sux = hmax(sm.dep[2], esx), sun = hmin(sm.dep[3], esn);
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            const int r = r0 + i;
+            if (r < len) {
+              sm.xs[lds_idx<T>(r)] = hmax(hmax(bx[i], sux), hmax(prx, ax[i]));
+              sm.hs[lds_idx<T>(r)] = hmin(hmin(bn[i], sun), hmin(prn, an[i]));
+            }
+          }
+          __syncthreads();
+          const int rs = (int)max((int64_t)0, (w - 1) - p0);  // first slot whose window starts at >= 0
+          if (s.omax) chunk_store<T>(s.omax + (p0 - w + 1), sm.xs, rs, len);
+          if (s.omin) chunk_store<T>(s.omin + (p0 - w + 1), sm.hs, rs, len);
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -1388,6 +1474,8 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_col1(Series<T> s, uint6
         cur[i] = nxt[i];
       }
     }
+    if constexpr (DEFER)
+      if (pend) flush(pb);
   }
   // the last workgroup out bumps the epoch (no record of this launch
   // validates in the next one)
@@ -2158,13 +2246,18 @@ static hipError_t launch_long_v(const Series<T>& s, int64_t nch, int64_t K, T* a
 
 template <class T, int V>
 static hipError_t launch_long1_v(Series<T> s, int64_t K, uint64_t* rec, Ctl* ctl, hipStream_t st) {
+  // outputs a step behind the records from K = 32 chunks per block on
+  // (MAXMIN_LONG_DEFER=0 / =1 forces either: experiments, tests)
+  const char* ed = getenv("MAXMIN_LONG_DEFER");
+  const bool defer = ed ? ed[0] != '0' : K >= 32;
+  auto* kern = defer ? &k_chunk_col1<T, V, true> : &k_chunk_col1<T, V, false>;
   // every workgroup resident: a multiple of K no larger than the device holds
-  const int64_t cap = occupancy_grid(k_chunk_col1<T, V>, kChunkThreads);
+  const int64_t cap = occupancy_grid(kern, kChunkThreads);
   const int64_t g = cap / K * K;
   if (g < K) return hipErrorNotSupported;  // fewer slots than one column group
   void* args[] = {(void*)&s, (void*)&rec, (void*)&ctl};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_chunk_col1<T, V>), dim3((unsigned)g),
-                                    dim3(kChunkThreads), args, 0, st);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)g), dim3(kChunkThreads),
+                                    args, 0, st);
 }
 
 static size_t elem_size(int dtype) { return dtype == 1 ? 8 : (dtype == 3 ? 2 : 4); }

@@ -118,17 +118,23 @@ def test_misaligned_outputs():
                 assert_bits_equal(to_host(bmn[on:on + no], dt), omn, "min offsets %d/%d/%d" % (oi, ox, on))
 
 
-@pytest.mark.parametrize("path", ["onepass", "twopass", "lookback"])
+@pytest.mark.parametrize("path", ["onepass", "onepass-now", "onepass-defer", "twopass", "lookback"])
 @pytest.mark.parametrize("strategy", [mm.STRATEGY_AUTO, mm.STRATEGY_CHUNK, mm.STRATEGY_RUN], ids=["auto", "chunk", "run"])
 def test_large_windows(strategy, path, monkeypatch):
     """Windows of more than one chunk: the one-pass column kernel (records
-    between sibling workgroups), the two passes (MAXMIN_LONG_ONEPASS=0:
-    aggregates, then columns) and the look-back chunk kernel
-    (MAXMIN_LONG_LOOKBACK=1); every dtype, block counts from one to dozens
-    with a ragged last block, and a window longer than 256 chunks."""
+    between sibling workgroups; its outputs stored in the step of their
+    records or, MAXMIN_LONG_DEFER=1, one step later -- by default from 32
+    chunks per block), the two passes (MAXMIN_LONG_ONEPASS=0: aggregates,
+    then columns) and the look-back chunk kernel (MAXMIN_LONG_LOOKBACK=1);
+    every dtype, block counts from one to dozens with a ragged last block,
+    and a window longer than 256 chunks."""
     lookback = "1" if path == "lookback" else "0"
     monkeypatch.setenv("MAXMIN_LONG_LOOKBACK", lookback)
     monkeypatch.setenv("MAXMIN_LONG_ONEPASS", "0" if path == "twopass" else "1")
+    if path == "onepass":
+        monkeypatch.delenv("MAXMIN_LONG_DEFER", raising=False)
+    else:
+        monkeypatch.setenv("MAXMIN_LONG_DEFER", "1" if path == "onepass-defer" else "0")
     rng = synth.rng_for("tests", 104)
     a = gen(300000, np.float32, rng, "walk")
     for w in (2048, 4096, 4100, 65536, 100000, 299999, 300000):
