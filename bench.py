@@ -61,11 +61,14 @@ def kernel_name(strategy, w):
     tile kernel (last template argument: how many sub-tiles after its start
     a window may end), or for w > 8192 the one-pass long-window kernel
     (columns of 4096-element chunks; 8 elements per thread when a window
-    spans at most three chunks, else 16)."""
+    spans at most three chunks, else 16; outputs one step behind the
+    records from 32 chunks per block on)."""
     if strategy == "tile":
         return "mm::k_tile<0, float, false, %d>" % (1 if w <= 2048 else (w + 2047) // 2048)
     k = (w + 4095) // 4096
-    return "mm::k_chunk_col1<float, %d>" % (8 if k <= 3 else 16)
+    v = 8 if k <= 3 else 16
+    chunks = (w + 256 * v - 1) // (256 * v)
+    return "mm::k_chunk_col1<float, %d, %s>" % (v, "true" if chunks >= 32 else "false")
 
 
 # Sources whose change invalidates counter-derived traffic figures.
