@@ -678,17 +678,18 @@ hipError_t f2d_launch(int dtype, const void* d_in, const void* d_in2, int64_t ld
   // bands: about four waves per SIMD over the chip when the image allows,
   // at least 4B rows each so the w_rows-1 halo rows stay a small share;
   // for w_rows < 4 at most 16 rows and for 16-bit data with 8 <= w_rows <
-  // 16 at most 32 (MI355X, 8192^2: w = 3 float32 0.215 -> 0.186 ms, uint16
-  // 0.139 -> 0.124 against the rule's 64- and 32-row bands; uint16 w = 11 /
-  // 15 0.24 -> 0.21 / 0.22 against 64 rows; elsewhere the rule's bands were
-  // within 2% of the best)
+  // 16 and both outputs at most 32 (MI355X, 8192^2: w = 3 float32 0.215 ->
+  // 0.186 ms, uint16 0.139 -> 0.124 against the rule's 64- and 32-row
+  // bands; uint16 w = 11 / 15 0.24 -> 0.21 / 0.22 against 64 rows, while
+  // one output keeps 64: 0.121 against 0.136 ms at w = 15; elsewhere the
+  // rule's bands were within 2% of the best, one output or two)
   int64_t TR = band_rows;
   if (TR <= 0) {
     const int64_t target = 4 * 4 * 256;
     const int64_t bands = std::max<int64_t>(1, target / strips);
     TR = std::max<int64_t>((orows + bands - 1) / bands, 4 * B);
     if (B <= 2) TR = std::min<int64_t>(TR, 16);
-    if (dtype == 3 && B == 8) TR = std::min<int64_t>(TR, 32);
+    if (dtype == 3 && B == 8 && OUT == 3) TR = std::min<int64_t>(TR, 32);
   }
   TR = std::min<int64_t>(TR, orows);
   if (TR > (1 << 30)) return hipErrorNotSupported;
