@@ -173,3 +173,13 @@ def test_2d_column_passes(dt, cpass, monkeypatch):
         assert_bits_equal(to_host(bn[:, 3:ocol + 3], dt), omn, "offset min")
         assert_bits_equal(to_host(gx, dt), omx, "max-only")
         assert_bits_equal(to_host(gn, dt), omn, "min-only")
+    # a single output column (every lane group cut by the image edge) and
+    # one or two output rows
+    for wr in (16, 33, 64):
+        for rows, cols, wc in ((wr, 2, 2), (wr + 1, 3, 3), (wr + 1, 1, 1)):
+            a = _image(rows, cols, dt, rng)
+            note("2d cols=%s dt=%s tiny %dx%d w=%dx%d" % (cpass, np.dtype(dt).name, rows, cols, wr, wc))
+            gmx, gmn = mm.maxmin_filter_2d(to_dev(a), wr, wc)
+            omx, omn = oracle.filter2d(a, wr, wc)
+            assert_bits_equal(to_host(gmx, dt), omx, "tiny max %dx%d" % (wr, wc))
+            assert_bits_equal(to_host(gmn, dt), omn, "tiny min %dx%d" % (wr, wc))
